@@ -1,0 +1,188 @@
+/*
+ * amm.h -- C ABI of the MI355X (gfx950) Monte Carlo library for the
+ * forest-subtracted anomalous-magnetic-moment (AMM) integrands of QED graphs
+ * without lepton loops (S. Volkov, arXiv:1909.08015).
+ *
+ * Conventions shared by every entry point
+ *   - Return value: 0 on success, a negative AMM_E_* code on failure; the
+ *     message of the last failure on the calling thread is amm_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - Pointers documented as "device" must point to device memory of the
+ *     context's device (e.g. a torch tensor's data_ptr()); "host" pointers are
+ *     ordinary host memory.  The caller owns every pointer it passes; the
+ *     context owns what it allocates and frees it in amm_destroy.
+ *   - A stream argument is a hipStream_t passed as void* (NULL = default
+ *     stream).  Calls that take a stream enqueue work and return; the results
+ *     are valid after the stream is synchronised (amm_read synchronises).
+ *   - Parameter numbering of an n-loop SE graph (M = 3n-1 parameters):
+ *     electron segments 0..2n-2 along the line, then the n photons in the
+ *     order of the graph's sorted chord list.  The insertion e of the external
+ *     photon into segment e merges the two lines next to it into parameter e
+ *     (Sec. III.A, footnote on the 3n -> 3n-1 reduction).
+ *   - Graph ids: SE graphs of one loop order in lexicographic order of their
+ *     sorted chord lists.
+ */
+#ifndef AMM_H
+#define AMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AMM_OK            0
+#define AMM_E_ARG        -1   /* bad argument or call order                 */
+#define AMM_E_NOTBUILT   -2   /* tables not built yet                       */
+#define AMM_E_HIP        -3   /* a HIP runtime call failed                  */
+#define AMM_E_NOMEM      -4   /* allocation failed                          */
+#define AMM_E_NUMERIC    -5   /* a numeric invariant failed on the host     */
+#define AMM_E_TOOBIG     -6   /* size beyond the library's stated maximum   */
+
+typedef struct amm_ctx amm_ctx;
+
+/* Density constants.  Sec. III.A eq. (mc_settings): the six Deg(s)
+ * constants; Sec. V: mixture weights c[0..3] = C1..C4 and D (Calc 2:
+ * C2 = 0.03, C3 = 0.01, C4 = 0.06, D = 0.75, C1 = 1 - C2 - C3 - C4). */
+typedef struct {
+    double cbigz, cbigf, cadd, csubi, csubse, csubo;
+    double c[4];
+    double d;
+} amm_density_params;
+
+/* One Monte Carlo run over a range of graphs (Sec. III.B, eq.
+ * integral_approx).  Samples counter0 .. counter0+n_per_graph-1 of every graph
+ * in [graph_begin, graph_end) are evaluated.
+ *   sampler:     0 plain density g; 1 learned mixture q = (q_theta + g)/2
+ *                (falls back to plain if no trained table exists).
+ *   accept_tau:  per-graph round-off acceptance threshold of eq.
+ *                (interval_accept) as a host array of length graph_end -
+ *                graph_begin, or NULL for no flagging.
+ *   force_flag:  1 = recompute every point in double-double.
+ *   samples_per_thread: 0 = autotuned value for the loop order.
+ *   accumulate:  0 = reset the accumulators of these graphs first. */
+typedef struct {
+    uint64_t seed;
+    uint64_t counter0;
+    uint64_t n_per_graph;
+    int graph_begin, graph_end;
+    int sampler;
+    int force_flag;
+    int samples_per_thread;
+    int accumulate;
+    const double *accept_tau;
+} amm_run_params;
+
+/* Accumulators of one insertion (vertex graph) or one class. */
+typedef struct {
+    double mean, sigma;                 /* eq. (integral_approx), eq. (sigma_down) */
+    double sum_y, sum_y2, sum_abs;
+    uint64_t n, n_flag, n_dd_fail, n_ood;
+} amm_estimate;
+
+/* Static cost of evaluating one sample of an SE graph. */
+typedef struct {
+    int n_insertions;
+    int n_terms;            /* forest terms (L-U merged) over all insertions */
+    int n_terms_expanded;   /* with (L-U) split in two, Sec. II counting     */
+    int n_level_evals;      /* level evaluations per sample                  */
+    int64_t n_monomials;    /* numerator monomials evaluated per sample      */
+    double flops_per_sample;/* algorithmic FP64 flops per sample, FMA = 2    */
+} amm_plan_info;
+
+/* Create a context on HIP device `device`. */
+int amm_create(amm_ctx **out, int device);
+/* Free everything the context allocated. */
+void amm_destroy(amm_ctx *ctx);
+/* Message of the last error on this thread ("" if none). */
+const char *amm_last_error(void);
+
+/* Enumerate the n-loop SE graphs without lepton loops (1 <= loops <= 5):
+ * counts per Sec. I (3213 vertex graphs at 5 loops modulo reversal). Outputs
+ * may be NULL. n_vertex counts oriented vertex graphs (SE graph x insertion). */
+int amm_enumerate(amm_ctx *ctx, int loops, int *n_se, int *n_vertex, int *M);
+
+/* Chords (2*loops ints, pairs of vertex positions 0..2n-1) and the class
+ * (k, m, m') of each insertion ((2n-1)*3 ints; Sec. V definition before
+ * Table I) of SE graph g.  Host pointers; either may be NULL. */
+int amm_graph_desc(const amm_ctx *ctx, int g, int *chords, int *classes);
+
+/* Build the per-graph density tables (Sec. III.A) and subtraction tables
+ * (Sec. II forest formula) for graphs [graph_begin, graph_end) of the
+ * enumerated loop order and upload them once.  params NULL = Calc 2. */
+int amm_build_tables(amm_ctx *ctx, const amm_density_params *params,
+                     int graph_begin, int graph_end);
+
+/* Static plan statistics of graph g (after amm_build_tables). */
+int amm_plan_stats(const amm_ctx *ctx, int g, amm_plan_info *out);
+
+/* Sample n points of graph g: sample indices counter0..counter0+n-1.
+ * Device outputs (any may be NULL): z [n x M] doubles, gx [n] mantissa and
+ * gj [n] int32 exponent of g = gx 2^gj (Sec. IV.A), path [n x M] int32 line
+ * order z_{path0} >= z_{path1} >= ..., comp [n] int32 mixture component. */
+int amm_sample(amm_ctx *ctx, int g, uint64_t seed, uint64_t counter0, uint64_t n,
+               double *z, double *gx, int32_t *gj, int32_t *path, int32_t *comp,
+               void *stream);
+
+/* Evaluate the integrands of all 2n-1 insertions of graph g at n device
+ * points z [n x M]: I [n x (2n-1)] and the sum of |term| per insertion
+ * absI [n x (2n-1)] (either may be NULL).  precision: 0 = FP64,
+ * 1 = double-double (value rounded to double). */
+int amm_eval(amm_ctx *ctx, int g, const double *z, uint64_t n,
+             double *I, double *absI, int precision, void *stream);
+
+/* Run the Monte Carlo (sample, evaluate, round-off check, double-double
+ * recompute of flagged points, accumulate) asynchronously on `stream`. */
+int amm_integrate(amm_ctx *ctx, const amm_run_params *run, void *stream);
+
+/* Read accumulators (synchronises the last stream used).  g >= 0 selects a
+ * graph; e >= 0 an insertion of it, e = -1 the sum over its insertions.
+ * cls_k >= 0 with g = -1 selects a class (k, m, m') summed over all built
+ * graphs (class sigma^2 adds over graphs, eq. sigma_sum). */
+int amm_read(amm_ctx *ctx, int g, int e, int cls_k, int cls_m, int cls_mp,
+             amm_estimate *out);
+
+/* Per-phase device timing of amm_integrate with HIP events recorded on the
+ * launch stream.  enable = 1 starts recording (and resets the totals),
+ * 0 stops.  Outputs (host, may be NULL) are totals since enabling:
+ * milliseconds in the FP64 sample+integrand kernel, in the double-double
+ * recompute kernel, in the reduction kernel, and the number of FP64 kernel
+ * launches and of samples they processed.  Reading synchronises. */
+int amm_profile(amm_ctx *ctx, int enable, double *ms_fp64, double *ms_dd, double *ms_reduce,
+                int64_t *n_launches, int64_t *n_samples);
+
+/* ----- learned sector sampler (spec extension, not in the paper) -----
+ * A 3-layer FP32 MLP maps features of (graph, s, j) to a logit correction of
+ * the plain sector probabilities; q = (q_theta + g)/2 stays exactly
+ * computable so f/q remains unbiased. */
+
+/* Record pilot statistics: for `n_per_graph` samples of graphs
+ * [graph_begin, graph_end) drawn from the plain density with `seed`,
+ * accumulate W(s, j) = sum |f|/g over samples whose sector path takes line j
+ * from set s. */
+int amm_pilot(amm_ctx *ctx, uint64_t seed, uint64_t n_per_graph,
+              int graph_begin, int graph_end, void *stream);
+/* Train the MLP on the pilot table for `epochs` full-batch Adam steps with
+ * learning rate lr, then tabulate P_theta(j | s) for every built graph. */
+int amm_mlp_train(amm_ctx *ctx, int epochs, float lr, uint64_t init_seed, void *stream);
+/* Number of MLP parameters; copy them (FP32) to host buffer (NULL = count only). */
+int amm_mlp_params(const amm_ctx *ctx, float *host, size_t cap, size_t *count);
+/* Set MLP parameters from a host buffer of `count` floats. */
+int amm_mlp_set_params(amm_ctx *ctx, const float *host, size_t count);
+/* Feature rows of graph g: rows [n_rows x 16] (s, j) features, host output;
+ * row r corresponds to (s = mask_of_row[r], j = line_of_row[r]). */
+int amm_mlp_features(const amm_ctx *ctx, int g, float *rows, int32_t *mask_of_row,
+                     int32_t *line_of_row, size_t cap, size_t *n_rows);
+/* One forward+backward pass of the MLP loss on device rows (for gradient
+ * checks): rows [n x 16], row weights w [n], group id of each row grp [n]
+ * (rows of one (graph, s) group form one softmax), prior log-probabilities
+ * lp0 [n]; outputs loss (device, 1 float) and gradient (device, count floats). */
+int amm_mlp_loss_grad(amm_ctx *ctx, const float *rows, const float *w, const int32_t *grp,
+                      const float *lp0, int n_rows, int n_groups, float *loss, float *grad,
+                      void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMM_H */

@@ -125,10 +125,14 @@ def _comm_mu_q(q):
     return [(1, [('idx', 'mu'), q]), (-1, [q, ('idx', 'mu')])]
 
 
-@lru_cache(maxsize=None)
+_POLY_STORE = {}
+
+
 def _level_poly_cached(key):
-    items, op, kind = key
-    return _level_poly(list(items), op, kind)
+    if key not in _POLY_STORE:
+        items, op, kind = key
+        _POLY_STORE[key] = _level_poly(list(items), op, kind)
+    return _POLY_STORE[key]
 
 
 def _level_poly(items, op, kind):
@@ -431,3 +435,36 @@ def se_integrands(n, gi, z, exact=False):
         vg = G.make_vertex_graph(ch, e)
         out.append(vertex_integrand(vg, z, exact))
     return out
+
+
+# ----------------------------------------------------------------------------
+# Persisting the oracle's own level polynomials (they are slow to derive with
+# explicit matrices).  Only files written by dump_poly_cache are read back.
+# ----------------------------------------------------------------------------
+
+def _key_to_str(key):
+    return repr(key)
+
+
+def dump_poly_cache(path):
+    import gzip
+    import json
+    out = {}
+    for key in list(_POLY_STORE.keys()):
+        polys = _POLY_STORE[key]
+        out[_key_to_str(key)] = {name: [[list(map(list, m[0])), list(m[1]), m[2], f'{c.numerator}/{c.denominator}']
+                                        for m, c in d.items()] for name, d in polys.items()}
+    with gzip.open(path, 'wt') as f:
+        json.dump(out, f)
+
+
+def load_poly_cache(path):
+    import ast
+    import gzip
+    import json
+    with gzip.open(path, 'rt') as f:
+        data = json.load(f)
+    for ks, polys in data.items():
+        key = ast.literal_eval(ks)
+        _POLY_STORE[key] = {name: {(tuple(tuple(p) for p in m[0]), tuple(m[1]), m[2]): Fraction(m[3])
+                                   for m in lst} for name, lst in polys.items()}

@@ -1,0 +1,206 @@
+"""Thin ctypes binding of libamm (include/amm.h).  Argument marshalling only:
+every step of the Monte Carlo path runs in the library's HIP kernels.  Device
+buffers are torch CUDA tensors; streams are torch streams.  Import fails loudly
+when libamm.so has not been built."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, 'libamm.so')
+
+AMM_OK = 0
+
+
+class AmmError(RuntimeError):
+    pass
+
+
+class DensityParams(C.Structure):
+    _fields_ = [('cbigz', C.c_double), ('cbigf', C.c_double), ('cadd', C.c_double),
+                ('csubi', C.c_double), ('csubse', C.c_double), ('csubo', C.c_double),
+                ('c', C.c_double * 4), ('d', C.c_double)]
+
+
+class RunParams(C.Structure):
+    _fields_ = [('seed', C.c_uint64), ('counter0', C.c_uint64), ('n_per_graph', C.c_uint64),
+                ('graph_begin', C.c_int), ('graph_end', C.c_int), ('sampler', C.c_int),
+                ('force_flag', C.c_int), ('samples_per_thread', C.c_int), ('accumulate', C.c_int),
+                ('accept_tau', C.POINTER(C.c_double))]
+
+
+class Estimate(C.Structure):
+    _fields_ = [('mean', C.c_double), ('sigma', C.c_double), ('sum_y', C.c_double),
+                ('sum_y2', C.c_double), ('sum_abs', C.c_double), ('n', C.c_uint64),
+                ('n_flag', C.c_uint64), ('n_dd_fail', C.c_uint64), ('n_ood', C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [('n_insertions', C.c_int), ('n_terms', C.c_int), ('n_terms_expanded', C.c_int),
+                ('n_level_evals', C.c_int), ('n_monomials', C.c_int64),
+                ('flops_per_sample', C.c_double)]
+
+
+_lib = None
+
+SYMBOLS = {
+    'amm_create': (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
+    'amm_destroy': (None, [C.c_void_p]),
+    'amm_last_error': (C.c_char_p, []),
+    'amm_enumerate': (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    'amm_graph_desc': (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    'amm_build_tables': (C.c_int, [C.c_void_p, C.POINTER(DensityParams), C.c_int, C.c_int]),
+    'amm_plan_stats': (C.c_int, [C.c_void_p, C.c_int, C.POINTER(PlanInfo)]),
+    'amm_sample': (C.c_int, [C.c_void_p, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    'amm_eval': (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_int,
+                           C.c_void_p]),
+    'amm_integrate': (C.c_int, [C.c_void_p, C.POINTER(RunParams), C.c_void_p]),
+    'amm_read': (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Estimate)]),
+    'amm_profile': (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                              C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    'amm_pilot': (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64, C.c_int, C.c_int, C.c_void_p]),
+    'amm_mlp_train': (C.c_int, [C.c_void_p, C.c_int, C.c_float, C.c_uint64, C.c_void_p]),
+    'amm_mlp_params': (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    'amm_mlp_set_params': (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    'amm_mlp_features': (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                   C.POINTER(C.c_size_t)]),
+    'amm_mlp_loss_grad': (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                    C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+}
+
+
+def lib():
+    """Load libamm.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise AmmError(f'{LIB_PATH} is not built; run paper_1909_08015_amd/build.py')
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SYMBOLS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != AMM_OK:
+        raise AmmError(f'{what} failed ({rc}): {lib().amm_last_error().decode()}')
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+CALC2 = dict(cbigz=0.256, cbigf=0.839, cadd=0.786, csubi=0.2, csubse=0.0, csubo=0.2,
+             c=(((1.0 - 0.03) - 0.01) - 0.06, 0.03, 0.01, 0.06), d=0.75)
+
+
+class Context:
+    """One library context on one device."""
+
+    def __init__(self, device=0):
+        h = C.c_void_p()
+        _check(lib().amm_create(C.byref(h), device), 'amm_create')
+        self.h = h
+        self.device = device
+        self.loops = None
+
+    def close(self):
+        if self.h:
+            lib().amm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def enumerate(self, loops):
+        a, b, m = C.c_int(), C.c_int(), C.c_int()
+        _check(lib().amm_enumerate(self.h, loops, C.byref(a), C.byref(b), C.byref(m)), 'amm_enumerate')
+        self.loops = loops
+        self.n_se, self.n_vertex, self.M = a.value, b.value, m.value
+        return self.n_se, self.n_vertex, self.M
+
+    def graph_desc(self, g):
+        n = self.loops
+        ch = (C.c_int * (2 * n))()
+        cl = (C.c_int * (3 * (2 * n - 1)))()
+        _check(lib().amm_graph_desc(self.h, g, ch, cl), 'amm_graph_desc')
+        chords = tuple(sorted((ch[2 * i], ch[2 * i + 1]) for i in range(n)))
+        classes = [tuple(cl[3 * e:3 * e + 3]) for e in range(2 * n - 1)]
+        return chords, classes
+
+    def build_tables(self, begin=0, end=None, params=None):
+        p = dict(CALC2, **(params or {}))
+        dp = DensityParams(p['cbigz'], p['cbigf'], p['cadd'], p['csubi'], p['csubse'], p['csubo'],
+                           (C.c_double * 4)(*p['c']), p['d'])
+        end = self.n_se if end is None else end
+        _check(lib().amm_build_tables(self.h, C.byref(dp), begin, end), 'amm_build_tables')
+
+    def plan_stats(self, g):
+        s = PlanInfo()
+        _check(lib().amm_plan_stats(self.h, g, C.byref(s)), 'amm_plan_stats')
+        return {k: getattr(s, k) for k, _ in s._fields_}
+
+    def sample(self, g, seed, counter0, n, stream=None):
+        import torch
+        dev = f'cuda:{self.device}'
+        M = self.M
+        z = torch.empty((n, M), dtype=torch.float64, device=dev)
+        gx = torch.empty(n, dtype=torch.float64, device=dev)
+        gj = torch.empty(n, dtype=torch.int32, device=dev)
+        path = torch.empty((n, M), dtype=torch.int32, device=dev)
+        comp = torch.empty(n, dtype=torch.int32, device=dev)
+        _check(lib().amm_sample(self.h, g, seed, counter0, n, _ptr(z), _ptr(gx), _ptr(gj), _ptr(path),
+                                _ptr(comp), _stream(stream)), 'amm_sample')
+        return dict(z=z, gx=gx, gj=gj, path=path, comp=comp)
+
+    def eval(self, g, z, precision=0, stream=None):
+        import torch
+        n = z.shape[0]
+        ne = 2 * self.loops - 1
+        I = torch.empty((n, ne), dtype=torch.float64, device=z.device)
+        A = torch.empty((n, ne), dtype=torch.float64, device=z.device)
+        zc = z.contiguous()
+        _check(lib().amm_eval(self.h, g, _ptr(zc), n, _ptr(I), _ptr(A), precision, _stream(stream)), 'amm_eval')
+        return I, A
+
+    def integrate(self, seed, n_per_graph, graph_begin=0, graph_end=None, counter0=0, sampler=0,
+                  force_flag=0, samples_per_thread=0, accumulate=0, accept_tau=None, stream=None):
+        graph_end = self.n_se if graph_end is None else graph_end
+        tau = None
+        if accept_tau is not None:
+            tau = (C.c_double * len(accept_tau))(*accept_tau)
+        rp = RunParams(seed, counter0, n_per_graph, graph_begin, graph_end, sampler, force_flag,
+                       samples_per_thread, accumulate,
+                       C.cast(tau, C.POINTER(C.c_double)) if tau is not None else None)
+        _check(lib().amm_integrate(self.h, C.byref(rp), _stream(stream)), 'amm_integrate')
+
+    def profile(self, enable):
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        n, s = C.c_int64(), C.c_int64()
+        _check(lib().amm_profile(self.h, int(enable), C.byref(a), C.byref(b), C.byref(c), C.byref(n), C.byref(s)),
+               'amm_profile')
+        return dict(ms_fp64=a.value, ms_dd=b.value, ms_reduce=c.value, launches=n.value, samples=s.value)
+
+    def read(self, g=-1, e=-1, cls=None):
+        est = Estimate()
+        k, m, mp = cls if cls is not None else (-1, -1, -1)
+        _check(lib().amm_read(self.h, g, e, k, m, mp, C.byref(est)), 'amm_read')
+        return est.as_dict()

@@ -1,0 +1,490 @@
+// amm_core.h -- per-sample device code: Philox, density sampling, level
+// quantities and the forest-term interpreter.  Written once for the HIP
+// kernels; every function is __host__ __device__.
+//
+// Paper references: sampling and density Sec. III.A (eq. pdf, pdf_final),
+// g stored as x 2^j Sec. IV.A, forest formula Sec. II, estimator Sec. III.B.
+#pragma once
+#include <math.h>
+#include <stdint.h>
+
+#include "amm_host.h"
+#include "amm_plan.h"
+
+#define AMM_HD __host__ __device__
+#define AMM_HDI __host__ __device__ __forceinline__
+
+namespace amm {
+
+// ---------------------------------------------------------------------------
+// Double-double arithmetic (Dekker; Knuth two-sum; two-product via fma), as in
+// Hida, Li & Bailey's quad-double library.  Used for recomputing flagged points.
+// ---------------------------------------------------------------------------
+struct dd {
+    double hi, lo;
+    AMM_HDI dd() : hi(0), lo(0) {}
+    AMM_HDI dd(double x) : hi(x), lo(0) {}
+    AMM_HDI dd(double h, double l) : hi(h), lo(l) {}
+};
+AMM_HDI dd two_sum(double a, double b) {
+    double s = a + b;
+    double bb = s - a;
+    double e = (a - (s - bb)) + (b - bb);
+    return dd(s, e);
+}
+AMM_HDI dd quick_two_sum(double a, double b) {
+    double s = a + b;
+    return dd(s, b - (s - a));
+}
+AMM_HDI dd two_prod(double a, double b) {
+    double p = a * b;
+    return dd(p, fma(a, b, -p));
+}
+AMM_HDI dd operator+(dd a, dd b) {
+    dd s = two_sum(a.hi, b.hi);
+    dd t = two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = quick_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return quick_two_sum(s.hi, s.lo);
+}
+AMM_HDI dd operator-(dd a) { return dd(-a.hi, -a.lo); }
+AMM_HDI dd operator-(dd a, dd b) { return a + (-b); }
+AMM_HDI dd operator*(dd a, dd b) {
+    dd p = two_prod(a.hi, b.hi);
+    p.lo += a.hi * b.lo + a.lo * b.hi;
+    return quick_two_sum(p.hi, p.lo);
+}
+AMM_HDI dd operator/(dd a, dd b) {
+    double q1 = a.hi / b.hi;
+    dd r = a - b * dd(q1);
+    double q2 = r.hi / b.hi;
+    r = r - b * dd(q2);
+    double q3 = r.hi / b.hi;
+    dd q = quick_two_sum(q1, q2);
+    return q + dd(q3);
+}
+AMM_HDI dd &operator+=(dd &a, dd b) { a = a + b; return a; }
+AMM_HDI dd &operator-=(dd &a, dd b) { a = a - b; return a; }
+AMM_HDI dd &operator*=(dd &a, dd b) { a = a * b; return a; }
+AMM_HDI double to_double(double x) { return x; }
+AMM_HDI double to_double(dd x) { return x.hi + x.lo; }
+AMM_HDI double absd(double x) { return fabs(x); }
+AMM_HDI dd absd(dd x) { return x.hi < 0 ? -x : x; }
+AMM_HDI double mul_add(double a, double b, double c) { return fma(a, b, c); }
+AMM_HDI dd mul_add(dd a, dd b, dd c) { return a * b + c; }
+
+// ---------------------------------------------------------------------------
+// exp / log with the fixed operation order (no contraction): Cody-Waite
+// reduction + degree-13 Taylor polynomial; atanh series for log.
+// ---------------------------------------------------------------------------
+#pragma clang fp contract(off)
+AMM_HDI double amm_exp(double x) {
+    if (x < -745.2) return 0.0;
+    if (x > 709.78) return INFINITY;
+    double k = rint(x * AMM_INV_LN2);
+    double r = (x - k * AMM_LN2_HI) - k * AMM_LN2_LO;
+    double p = amm_exp_c(13);
+#pragma unroll
+    for (int i = 12; i >= 0; --i) p = p * r + amm_exp_c(i);
+    return ldexp(p, (int)k);
+}
+AMM_HDI double amm_log(double x) {
+    int k;
+    double m = frexp(x, &k);
+    if (m < AMM_SQRT_HALF) { m = m * 2.0; k = k - 1; }
+    double f = (m - 1.0) / (m + 1.0);
+    double s = f * f;
+    double q = amm_log_d(11);
+#pragma unroll
+    for (int i = 10; i >= 0; --i) q = q * s + amm_log_d(i);
+    double lm = (2.0 * f) * q;
+    double kd = (double)k;
+    return (kd * AMM_LN2_LO + lm) + kd * AMM_LN2_HI;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and the uniform conversion.
+// ---------------------------------------------------------------------------
+AMM_HDI void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+}
+AMM_HDI double uniform52(uint32_t a, uint32_t b) {
+    return ((double)(a >> 6) * 67108864.0 + (double)(b >> 6) + 0.5) * 0x1p-52;
+}
+AMM_HDI void uniforms(uint64_t seed, uint32_t uid, uint64_t idx, int count, double *u) {
+    uint32_t k0 = (uint32_t)(seed & 0xffffffffu) ^ uid, k1 = (uint32_t)(seed >> 32);
+    for (int b = 0; 2 * b < count; ++b) {
+        uint32_t c[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), (uint32_t)b, 0u};
+        philox4x32_10(c, k0, k1);
+        u[2 * b] = uniform52(c[0], c[1]);
+        if (2 * b + 1 < count) u[2 * b + 1] = uniform52(c[2], c[3]);
+    }
+}
+
+AMM_HDI int popc(uint32_t x) {
+    int c = 0;
+    while (x) { x &= x - 1; ++c; }
+    return c;
+}
+
+struct DensityDev {
+    const double *deg1, *deg3, *W1, *logdeg1;
+    double logK[4], logc[4], c[4];
+    const float *ptheta;      // learned P_theta(j | s) table [2^M * M] or null
+    double logc_mix;          // unused placeholder for alignment
+};
+
+struct SampleOut {
+    int comp;
+    int ood;
+    int gj;
+    double gx;
+};
+
+// Sample one point of an M-parameter graph from u[0 .. 2M-2] (Sec. III.A
+// sampling reading: mixture component, sector path, t = u^{1/Deg}).
+// z[M] receives the point, path[M] the line order.
+template <int M>
+AMM_HDI SampleOut sample_point(const DensityDev &D, const double *u, double *z, int *path) {
+    SampleOut o;
+    const uint32_t full = (1u << M) - 1u;
+    // mixture component
+    double thr = u[0], cum = 0.0;
+    int comp = 3;
+    bool chosen = false;
+    for (int ci = 0; ci < 4; ++ci) {
+        cum = cum + D.c[ci];
+        if (!chosen && thr < cum) { comp = ci; chosen = true; }
+    }
+    o.comp = comp;
+    bool uni = (comp == 1) || (comp == 3);
+    uint32_t s = full;
+    for (int l = 0; l < M - 1; ++l) {
+        double ul = u[1 + l];
+        int pick;
+        if (!uni) {
+            double total = 0.0;
+            for (int j = 0; j < M; ++j)
+                if ((s >> j) & 1u) total = total + D.W1[s & ~(1u << j)];
+            double t = ul * total;
+            double cw = 0.0;
+            pick = -1;
+            int last = -1;
+            for (int j = 0; j < M; ++j) {
+                if (!((s >> j) & 1u)) continue;
+                cw = cw + D.W1[s & ~(1u << j)];
+                if (pick < 0 && t < cw) pick = j;
+                last = j;
+            }
+            if (pick < 0) pick = last;
+        } else {
+            int size = popc(s);
+            int k = (int)floor(ul * (double)size);
+            int cnt = 0;
+            pick = -1;
+            for (int j = 0; j < M; ++j) {
+                if (!((s >> j) & 1u)) continue;
+                if (pick < 0 && cnt == k) pick = j;
+                ++cnt;
+            }
+        }
+        path[l] = pick;
+        s &= ~(1u << pick);
+    }
+    for (int j = 0; j < M; ++j)
+        if ((s >> j) & 1u) path[M - 1] = j;
+    // continuous part
+    uint32_t masks[M];
+    uint32_t acc = 0;
+    for (int l = M - 1; l >= 0; --l) { acc |= 1u << path[l]; masks[l] = acc; }
+    double logt[M];
+    logt[0] = 0.0;
+    for (int l = 1; l < M; ++l) {
+        uint32_t sl = masks[l];
+        double dsel;
+        if (comp == 1) dsel = (double)popc(sl);
+        else if (comp == 2) dsel = D.deg3[sl];
+        else dsel = D.deg1[sl];
+        logt[l] = amm_log(u[M + l - 1]) / dsel;
+    }
+    double p[M], lp[M];
+    p[0] = 1.0; lp[0] = 0.0;
+    for (int l = 1; l < M; ++l) {
+        double tt = amm_exp(logt[l]);
+        p[l] = p[l - 1] * tt;
+        lp[l] = lp[l - 1] + logt[l];
+    }
+    double norm = 0.0;
+    for (int l = 0; l < M; ++l) norm = norm + p[l];
+    double zmin = INFINITY;
+    for (int l = 0; l < M; ++l) {
+        double zl = p[l] / norm;
+        z[path[l]] = zl;
+        zmin = zl < zmin ? zl : zmin;
+    }
+    o.ood = !(zmin >= 2.2250738585072014e-308);
+    double lognorm = amm_log(norm);
+    double sumlogz = 0.0;
+    for (int l = 0; l < M; ++l) sumlogz = sumlogz + lp[l];
+    sumlogz = sumlogz - (double)M * lognorm;
+    double E0 = 0.0, E1 = 0.0, E2 = 0.0, lds = 0.0;
+    for (int l = 1; l < M; ++l) {
+        uint32_t sl = masks[l];
+        E0 = E0 + D.deg1[sl] * logt[l];
+        E1 = E1 + (double)popc(sl) * logt[l];
+        E2 = E2 + D.deg3[sl] * logt[l];
+        lds = lds + D.logdeg1[sl];
+    }
+    double Lc[4];
+    Lc[0] = (D.logc[0] + D.logK[0]) + E0;
+    Lc[1] = (D.logc[1] + D.logK[1]) + E1;
+    Lc[2] = (D.logc[2] + D.logK[2]) + E2;
+    Lc[3] = ((D.logc[3] + D.logK[3]) + E0) + lds;
+    double a = Lc[0] > Lc[1] ? Lc[0] : Lc[1];
+    double b = Lc[2] > Lc[3] ? Lc[2] : Lc[3];
+    double Lmax = a > b ? a : b;
+    double S = 0.0;
+    for (int ci = 0; ci < 4; ++ci) S = S + amm_exp(Lc[ci] - Lmax);
+    double Ltot = Lmax - sumlogz;
+    double k = rint(Ltot * AMM_INV_LN2);
+    double r = (Ltot - k * AMM_LN2_HI) - k * AMM_LN2_LO;
+    double x0 = amm_exp(r) * S;
+    int e;
+    double xm = frexp(x0, &e);
+    o.gx = xm;
+    o.gj = (int)k + e;
+    return o;
+}
+#pragma clang fp contract(on)
+
+// ---------------------------------------------------------------------------
+// Integrand: level quantities (LDL^T of the loop matrix), numerator
+// polynomials, children combination, term sum.
+// ---------------------------------------------------------------------------
+struct PlanDev {
+    const LevelDesc *levels;
+    const TermDesc *terms;
+    const int32_t *ops;
+    const Mono *monos;
+    const int2 *ranges;
+    int nterms;
+    int n;
+    int ninsert;
+};
+
+template <int N> struct Dims {
+    static constexpr int KM = 2 * N;
+    static constexpr int NV = KM * (KM + 1) / 2 + 2 * KM;
+    static constexpr int DEPTH = 2 * N + 1;
+};
+
+// Truncated convolution of two c-vectors of length N.
+template <typename T, int N>
+AMM_HDI void conv_into(const T *a, const T *b, T *out) {
+    for (int c = 0; c < N; ++c) {
+        T s = T(0.0);
+        for (int i = 0; i <= c; ++i) s = mul_add(a[i], b[c - i], s);
+        out[c] = s;
+    }
+}
+
+// Evaluate one level: returns c-vectors per output (out[o][c]) given the
+// children's values on the stack.  Adds the level's V to vtot.
+template <typename T, int N>
+AMM_HDI void eval_level(const PlanDev &P, const LevelDesc &d, const double *z,
+                        T (*stk)[2][N], int &sp, T &vtot) {
+    constexpr int KM = Dims<N>::KM;
+    const int K = d.K, L = d.L;
+    T zseg[KM + 1], zph[N];
+    for (int k = 1; k <= KM; ++k) {
+        if (k > K) break;
+        double zz = z[d.seg_param[k - 1]];
+        zseg[k] = d.seg_half[k - 1] ? T(zz * 0.5) : T(zz);
+    }
+    for (int a = 0; a < N; ++a) {
+        if (a >= L) break;
+        zph[a] = T(z[d.ph_param[a]]);
+    }
+    // loop matrix Lambda_ab = delta_ab z_gamma_a + sum_{k in span a & span b} z_k
+    T Lam[N][N];
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b) Lam[a][b] = T(0.0);
+    for (int a = 0; a < L; ++a) {
+        Lam[a][a] = zph[a];
+        for (int b = 0; b < L; ++b) {
+            uint32_t both = d.span[a] & d.span[b];
+            for (int k = 1; k <= K; ++k)
+                if ((both >> (k - 1)) & 1u) Lam[a][b] += zseg[k];
+        }
+    }
+    // LDL^T
+    T Lw[N][N], D[N];
+    T U = T(1.0);
+    for (int i = 0; i < L; ++i) {
+        T di = Lam[i][i];
+        for (int j = 0; j < i; ++j) di -= Lw[i][j] * Lw[i][j] * D[j];
+        D[i] = di;
+        U *= di;
+        for (int r = i + 1; r < L; ++r) {
+            T v = Lam[r][i];
+            for (int j = 0; j < i; ++j) v -= Lw[r][j] * Lw[i][j] * D[j];
+            Lw[r][i] = v / di;
+        }
+    }
+    T Dinv[N];
+    for (int i = 0; i < L; ++i) Dinv[i] = T(1.0) / D[i];
+    // y_k = L^{-1} s_k
+    T y[KM + 1][N];
+    for (int k = 1; k <= K; ++k) {
+        for (int a = 0; a < L; ++a) {
+            T v = ((d.span[a] >> (k - 1)) & 1u) ? T(1.0) : T(0.0);
+            for (int b = 0; b < a; ++b) v -= Lw[a][b] * y[k][b];
+            y[k][a] = v;
+        }
+    }
+    // sigma, w = L^{-1} sigma, V = sum w^2/D
+    T w[N];
+    T V = T(0.0);
+    for (int a = 0; a < L; ++a) {
+        T sg = T(0.0);
+        for (int k = 1; k <= K; ++k)
+            if ((d.span[a] >> (k - 1)) & 1u) sg += zseg[k];
+        for (int b = 0; b < a; ++b) sg -= Lw[a][b] * w[b];
+        w[a] = sg;
+        V += w[a] * w[a] * Dinv[a];
+    }
+    vtot += V;
+    T vars[Dims<N>::NV];
+    const int XN = amm_xn(K);
+    for (int k = 1; k <= K; ++k) {
+        for (int k2 = k; k2 <= K; ++k2) {
+            T s = T(0.0);
+            for (int a = 0; a < L; ++a) s += y[k][a] * y[k2][a] * Dinv[a];
+            vars[amm_xidx(K, k, k2)] = s;
+        }
+        T s = T(0.0);
+        for (int a = 0; a < L; ++a) s += y[k][a] * w[a] * Dinv[a];
+        vars[XN + k - 1] = T(1.0) - s;
+    }
+    if (d.op == OP_A) {
+        T wc[N];
+        for (int a = 0; a < L; ++a) {
+            T jc = T(0.0);
+            for (int k = 1; k <= K; ++k)
+                if ((d.span[a] >> (k - 1)) & 1u) jc += zseg[k] * T(k <= d.ext_node ? -0.5 : 0.5);
+            for (int b = 0; b < a; ++b) jc -= Lw[a][b] * wc[b];
+            wc[a] = jc;
+        }
+        for (int k = 1; k <= K; ++k) {
+            T s = T(0.0);
+            for (int a = 0; a < L; ++a) s += y[k][a] * wc[a] * Dinv[a];
+            vars[XN + K + k - 1] = T(k <= d.ext_node ? -0.5 : 0.5) - s;
+        }
+    }
+    // prefactor per c: pref (-1/2)^c / U^2 (* z_e for the merged line)
+    T base = T(d.pref) / (U * U);
+    if (d.has_X) {
+        for (int k = 1; k <= K; ++k)
+            if (d.seg_half[k - 1]) { base = base * (zseg[k] + zseg[k]); break; }
+    }
+    // children: on stack at sp - nkids .. sp - 1 (node order)
+    const int nk = d.nkids;
+    const int kid0 = sp - nk;
+    T prodV[N];
+    prodV[0] = T(1.0);
+    for (int c = 1; c < N; ++c) prodV[c] = T(0.0);
+    for (int q = 0; q < nk; ++q) {
+        if ((d.kid_is_se >> q) & 1u) continue;
+        T tmp[N];
+        conv_into<T, N>(prodV, stk[kid0 + q][0], tmp);
+        for (int c = 0; c < N; ++c) prodV[c] = tmp[c];
+    }
+    T res[2][N];
+    for (int o = 0; o < 2; ++o)
+        for (int c = 0; c < N; ++c) res[o][c] = T(0.0);
+    for (int var = 0; var < d.nvariants; ++var) {
+        // product of SE children's chosen outputs
+        T sev[N];
+        for (int c = 0; c < N; ++c) sev[c] = prodV[c];
+        int bit = 0;
+        for (int q = 0; q < nk; ++q) {
+            if (!((d.kid_is_se >> q) & 1u)) continue;
+            int ch = (var >> bit) & 1;
+            ++bit;
+            T tmp[N];
+            conv_into<T, N>(sev, stk[kid0 + q][ch], tmp);
+            for (int c = 0; c < N; ++c) sev[c] = tmp[c];
+        }
+        for (int o = 0; o < d.nout; ++o) {
+            T own[N];
+            T fac = base;
+            for (int c = 0; c < N; ++c) {
+                int2 r = P.ranges[d.mono_range + (var * d.nout + o) * (P.n + 1) + c];
+                T acc = T(0.0);
+                for (int m = r.x; m < r.y; ++m) {
+                    const Mono &mo = P.monos[m];
+                    T t = mo.nv ? vars[mo.v[0]] : T(1.0);
+                    for (int i = 1; i < mo.nv; ++i) t = t * vars[mo.v[i]];
+                    acc = mul_add(T(mo.coef), t, acc);
+                }
+                own[c] = acc * fac;
+                fac = fac * T(-0.5);
+            }
+#ifdef AMM_DEBUG_LEVELS
+            printf("  level op%d var%d out%d own:", d.op, var, o);
+            for (int c = 0; c < N; ++c) printf(" %.10g", to_double(own[c]));
+            printf(" U %.10g V-so-far %.10g\n", to_double(U), to_double(vtot));
+#endif
+            T tmp[N];
+            conv_into<T, N>(own, sev, tmp);
+            for (int c = 0; c < N; ++c) res[o][c] += tmp[c];
+        }
+    }
+    sp = kid0;
+    for (int o = 0; o < 2; ++o)
+        for (int c = 0; c < N; ++c) stk[sp][o][c] = res[o][c];
+    ++sp;
+}
+
+// All insertion integrands of one SE graph at z: I[e], and sum |term| absI[e].
+template <typename T, int N>
+AMM_HDI void eval_graph(const PlanDev &P, const double *z, T *I, T *absI) {
+    for (int e = 0; e < P.ninsert; ++e) { I[e] = T(0.0); absI[e] = T(0.0); }
+    T stk[Dims<N>::DEPTH][2][N];
+    for (int t = 0; t < P.nterms; ++t) {
+        const TermDesc td = P.terms[t];
+        int sp = 0;
+        T vtot = T(0.0);
+        for (int o = td.op_begin; o < td.op_end; ++o) {
+            const LevelDesc &d = P.levels[P.ops[o]];
+            eval_level<T, N>(P, d, z, stk, sp, vtot);
+        }
+        // sum_c vec[c] Gamma(n-c) / V^{n-c}
+        T val = T(0.0);
+        T vinv = T(1.0) / vtot;
+        T vp = vinv;                     // V^-(n-c) built from c = n-1 down
+        double gam = 1.0;                // Gamma(n-c) = (n-c-1)!
+        for (int c = N - 1; c >= 0; --c) {
+            if (c < P.n) {
+                val = mul_add(stk[0][0][c] * T(gam), vp, val);
+                vp = vp * vinv;
+                gam = gam * (double)(P.n - c);
+            }
+        }
+        T sv = td.sign > 0 ? val : -val;
+        I[td.e] += sv;
+        absI[td.e] += absd(val);
+    }
+}
+
+}  // namespace amm

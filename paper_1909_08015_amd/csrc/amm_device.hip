@@ -1,0 +1,695 @@
+// amm_device.hip -- HIP kernels for gfx950 and the C ABI of libamm.
+//
+// Kernels (one thread = one sample, 256-thread blocks = 4 wave64):
+//   k_sample     Philox -> density sample (Sec. III.A) -> z, g = x 2^j
+//   k_eval       forest-subtracted integrands of all insertions at given z
+//   k_integrate  sample + evaluate + round-off check (eq. interval_accept) +
+//                per-chunk deterministic partial sums; flagged samples are
+//                compacted per chunk in sample order
+//   k_dd         double-double recompute of the flagged samples of a chunk
+//   k_reduce     fixed-order sum of chunk partials into graph accumulators
+// Sums are reduced in a fixed tree keyed by chunk, so results do not depend on
+// the grid size.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "amm_core.h"
+#include "amm_mlp.h"
+
+using namespace amm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                      \
+    do {                                                                               \
+        hipError_t e_ = (x);                                                           \
+        if (e_ != hipSuccess)                                                          \
+            return fail(AMM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+constexpr int BLOCK = 256;
+constexpr int RPC = 64;                       // rounds per chunk
+constexpr int CHUNK = BLOCK * RPC;            // samples per chunk
+constexpr int MAX_CHUNKS_PER_LAUNCH = 4096;
+constexpr double KAPPA = 64.0;                // round-off bound multiplier (reading R11)
+constexpr int MAXNE = 2 * MAXN - 1;
+constexpr int NSTAT_MAX = 3 * MAXNE + 2 * MAXNE + 4;
+
+struct GraphSlot {
+    bool built = false;
+    int n = 0, M = 0, ne = 0, ncls = 0;
+    int cls_of[MAXNE] = {0};
+    int cls_kmm[MAXNE][3];
+    uint32_t uid = 0;
+    PlanHost plan;
+    DensityTables dens;
+    // device copies
+    LevelDesc *d_levels = nullptr;
+    TermDesc *d_terms = nullptr;
+    int32_t *d_ops = nullptr;
+    Mono *d_monos = nullptr;
+    int2 *d_ranges = nullptr;
+    double *d_deg1 = nullptr, *d_deg3 = nullptr, *d_W1 = nullptr, *d_logdeg1 = nullptr;
+    float *d_ptheta = nullptr;                // learned P_theta(j|s) [2^M * M]
+    double *d_pilotW = nullptr;               // pilot W(s, j) [2^M * M]
+    // accumulators (host mirror after read)
+    std::vector<double> acc;                  // NSTAT
+    int nstat() const { return 3 * ne + 2 * ncls + 4; }
+    PlanDev plan_dev() const {
+        PlanDev p;
+        p.levels = d_levels; p.terms = d_terms; p.ops = d_ops; p.monos = d_monos; p.ranges = d_ranges;
+        p.nterms = (int)plan.terms.size(); p.n = n; p.ninsert = ne;
+        return p;
+    }
+    DensityDev dens_dev(bool learned) const {
+        DensityDev D;
+        D.deg1 = d_deg1; D.deg3 = d_deg3; D.W1 = d_W1; D.logdeg1 = d_logdeg1;
+        for (int c = 0; c < 4; ++c) { D.logK[c] = dens.logK[c]; D.logc[c] = dens.logc[c]; D.c[c] = dens.c[c]; }
+        D.ptheta = learned ? d_ptheta : nullptr;
+        D.logc_mix = 0;
+        return D;
+    }
+};
+
+}  // namespace
+
+struct amm_ctx {
+    int device = 0;
+    int loops = 0;
+    std::vector<SEGraph> graphs;
+    std::vector<GraphSlot> slots;
+    hipStream_t last_stream = nullptr;
+    double *d_acc = nullptr;            // [graphs * NSTAT_MAX]
+    double *d_part = nullptr;           // chunk partials [MAX_CHUNKS * NSTAT_MAX]
+    uint32_t *d_flag = nullptr;         // flagged offsets [MAX_CHUNKS * CHUNK]
+    int32_t *d_nflag = nullptr;         // per chunk
+    MlpState mlp;
+    // profiling
+    bool prof = false;
+    struct Ev { hipEvent_t a, b, c, d; int64_t samples; };
+    std::vector<Ev> evs;
+    double prof_ms[3] = {0, 0, 0};
+    int64_t prof_launch = 0, prof_samples = 0;
+    ~amm_ctx();
+};
+
+amm_ctx::~amm_ctx() {
+    hipSetDevice(device);
+    for (auto &s : slots) {
+        hipFree(s.d_levels); hipFree(s.d_terms); hipFree(s.d_ops); hipFree(s.d_monos); hipFree(s.d_ranges);
+        hipFree(s.d_deg1); hipFree(s.d_deg3); hipFree(s.d_W1); hipFree(s.d_logdeg1);
+        hipFree(s.d_ptheta); hipFree(s.d_pilotW);
+    }
+    hipFree(d_acc); hipFree(d_part); hipFree(d_flag); hipFree(d_nflag);
+    mlp_free(mlp);
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ void __launch_bounds__(BLOCK) k_sample(DensityDev D, uint32_t uid, uint64_t seed, uint64_t c0, uint64_t n,
+                                                  double *z, double *gx, int32_t *gj, int32_t *path, int32_t *comp) {
+    uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    double u[2 * M], zz[M];
+    int pp[M];
+    uniforms(seed, uid, c0 + i, 2 * M - 1, u);
+    SampleOut o = sample_point<M>(D, u, zz, pp);
+    if (z) for (int j = 0; j < M; ++j) z[i * M + j] = zz[j];
+    if (path) for (int j = 0; j < M; ++j) path[i * M + j] = pp[j];
+    if (gx) gx[i] = o.gx;
+    if (gj) gj[i] = o.gj;
+    if (comp) comp[i] = o.comp;
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(BLOCK) k_eval(PlanDev P, const double *z, uint64_t n, double *I, double *absI) {
+    constexpr int M = 3 * N - 1, NE = 2 * N - 1;
+    uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    double zz[M];
+    for (int j = 0; j < M; ++j) zz[j] = z[i * M + j];
+    T v[NE], a[NE];
+    eval_graph<T, N>(P, zz, v, a);
+    for (int e = 0; e < NE; ++e) {
+        if (I) I[i * NE + e] = to_double(v[e]);
+        if (absI) absI[i * NE + e] = to_double(a[e]);
+    }
+}
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+struct RunArgs {
+    uint64_t seed, begin, end;      // sample index range [begin, end)
+    uint32_t uid;
+    int chunk0;                     // first chunk (relative to begin) of this launch
+    int nchunks;
+    double tau;                     // acceptance threshold (<0: flag all; inf: none)
+    int ncls;
+    int cls_of[MAXNE];
+    int learned;
+};
+
+// Statistic layout per graph:
+//   [0, ne)        sum y_e       [ne, 2ne)  sum y_e^2     [2ne, 3ne) sum |y_e|
+//   [3ne, 3ne+c)   sum y_class   [.., +c)   sum y_class^2
+//   then n, n_flag, n_dd_fail, n_ood.
+template <int N>
+__device__ __forceinline__ void add_stats(double (&st)[3 * (2 * N - 1) + 2 * (2 * N - 1) + 4], const double *y,
+                                          const RunArgs &A) {
+    constexpr int NE = 2 * N - 1;
+    double yc[NE];
+    for (int c = 0; c < NE; ++c) yc[c] = 0.0;
+    for (int e = 0; e < NE; ++e) {
+        st[e] += y[e];
+        st[NE + e] += y[e] * y[e];
+        st[2 * NE + e] += fabs(y[e]);
+        for (int c = 0; c < NE; ++c)
+            if (A.cls_of[e] == c) yc[c] += y[e];
+    }
+    for (int c = 0; c < NE; ++c) {
+        if (c >= A.ncls) break;
+        st[3 * NE + c] += yc[c];
+        st[3 * NE + A.ncls + c] += yc[c] * yc[c];
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void eval_sample(const PlanDev &P, const DensityDev &D, const RunArgs &A, uint64_t idx,
+                                            double *y, int &ood, int &flag) {
+    constexpr int M = 3 * N - 1, NE = 2 * N - 1;
+    double u[2 * M], z[M];
+    int path[M];
+    uniforms(A.seed, A.uid, idx, 2 * M - 1, u);
+    SampleOut o = sample_point<M>(D, u, z, path);
+    ood = o.ood;
+    flag = 0;
+    if (o.ood) {
+        for (int e = 0; e < NE; ++e) y[e] = 0.0;
+        return;
+    }
+    double I[NE], aI[NE];
+    eval_graph<double, N>(P, z, I, aI);
+    for (int e = 0; e < NE; ++e) {
+        double ye = ldexp(I[e] / o.gx, -o.gj);
+        double r = KAPPA * 0x1p-53 * ldexp(aI[e] / o.gx, -o.gj);
+        if (!(r <= A.tau) || !isfinite(ye)) flag = 1;
+        y[e] = ye;
+    }
+    if (flag)
+        for (int e = 0; e < NE; ++e) y[e] = 0.0;
+}
+
+template <int N>
+__global__ void __launch_bounds__(BLOCK) k_integrate(PlanDev P, DensityDev D, RunArgs A, double *part, uint32_t *flags,
+                                                     int32_t *nflag) {
+    constexpr int NE = 2 * N - 1;
+    constexpr int NST = 3 * NE + 2 * NE + 4;
+    __shared__ double sh[BLOCK];
+    __shared__ int shc[BLOCK];
+    const int nst = 3 * NE + 2 * A.ncls + 4;
+    for (int ch = blockIdx.x; ch < A.nchunks; ch += gridDim.x) {
+        double st[NST];
+        for (int s = 0; s < NST; ++s) st[s] = 0.0;
+        uint64_t base = A.begin + (uint64_t)(A.chunk0 + ch) * CHUNK;
+        int fcount = 0;
+        for (int r = 0; r < RPC; ++r) {
+            uint64_t idx = base + (uint64_t)r * BLOCK + threadIdx.x;
+            int flag = 0, ood = 0;
+            double y[NE];
+            bool live = idx < A.end;
+            if (live) {
+                eval_sample<N>(P, D, A, idx, y, ood, flag);
+                add_stats<N>(st, y, A);
+                st[nst - 4] += 1.0;
+                st[nst - 3] += flag;
+                st[nst - 1] += ood;
+            }
+            // compact flagged offsets of this round in thread order
+            shc[threadIdx.x] = (live && flag) ? 1 : 0;
+            __syncthreads();
+            int pos = 0;
+            for (int t = 0; t < (int)threadIdx.x; ++t) pos += shc[t];
+            int tot = 0;
+            if (threadIdx.x == 0)
+                for (int t = 0; t < BLOCK; ++t) tot += shc[t];
+            if (live && flag) flags[(size_t)ch * CHUNK + fcount + pos] = (uint32_t)(r * BLOCK + threadIdx.x);
+            __syncthreads();
+            if (threadIdx.x == 0) shc[0] = tot;
+            __syncthreads();
+            fcount += shc[0];
+            __syncthreads();
+        }
+        for (int s = 0; s < nst; ++s) {
+            double v = block_sum(st[s], sh);
+            if (threadIdx.x == 0) part[(size_t)ch * NSTAT_MAX + s] = v;
+        }
+        if (threadIdx.x == 0) nflag[ch] = fcount;
+        __syncthreads();
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(BLOCK) k_dd(PlanDev P, DensityDev D, RunArgs A, double *part, const uint32_t *flags,
+                                              const int32_t *nflag) {
+    constexpr int M = 3 * N - 1, NE = 2 * N - 1;
+    constexpr int NST = 3 * NE + 2 * NE + 4;
+    __shared__ double sh[BLOCK];
+    const int nst = 3 * NE + 2 * A.ncls + 4;
+    for (int ch = blockIdx.x; ch < A.nchunks; ch += gridDim.x) {
+        int nf = nflag[ch];
+        if (nf == 0) continue;
+        double st[NST];
+        for (int s = 0; s < NST; ++s) st[s] = 0.0;
+        uint64_t base = A.begin + (uint64_t)(A.chunk0 + ch) * CHUNK;
+        for (int f = threadIdx.x; f < nf; f += BLOCK) {
+            uint64_t idx = base + flags[(size_t)ch * CHUNK + f];
+            double u[2 * M], z[M];
+            int path[M];
+            uniforms(A.seed, A.uid, idx, 2 * M - 1, u);
+            SampleOut o = sample_point<M>(D, u, z, path);
+            dd I[NE], aI[NE];
+            eval_graph<dd, N>(P, z, I, aI);
+            double y[NE];
+            int fail = 0;
+            for (int e = 0; e < NE; ++e) {
+                double ye = ldexp(to_double(I[e]) / o.gx, -o.gj);
+                double r = KAPPA * 0x1p-104 * ldexp(to_double(aI[e]) / o.gx, -o.gj);
+                if (!(r <= fabs(A.tau) || A.tau < 0) || !isfinite(ye)) fail = 1;
+                y[e] = ye;
+            }
+            if (fail) {
+                for (int e = 0; e < NE; ++e) y[e] = 0.0;
+                st[nst - 2] += 1.0;
+            }
+            add_stats<N>(st, y, A);
+        }
+        for (int s = 0; s < nst; ++s) {
+            double v = block_sum(st[s], sh);
+            if (threadIdx.x == 0) part[(size_t)ch * NSTAT_MAX + s] += v;
+        }
+    }
+}
+
+__global__ void k_reduce(const double *part, int nchunks, int nst, double *acc) {
+    int s = threadIdx.x;
+    if (s >= nst) return;
+    double v = 0.0;
+    for (int c = 0; c < nchunks; ++c) v += part[(size_t)c * NSTAT_MAX + s];
+    acc[s] += v;
+}
+
+__global__ void k_zero(double *p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Host helpers
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename X>
+int upload(X **dst, const X *src, size_t count) {
+    if (count == 0) count = 1;
+    HIPCHK(hipMalloc((void **)dst, count * sizeof(X)));
+    if (src) HIPCHK(hipMemcpy(*dst, src, count * sizeof(X), hipMemcpyHostToDevice));
+    return AMM_OK;
+}
+
+int grid_for(uint64_t n) { return (int)((n + BLOCK - 1) / BLOCK); }
+
+template <int N>
+void launch_eval(const PlanDev &P, const double *z, uint64_t n, double *I, double *a, int prec, hipStream_t s) {
+    if (prec) hipLaunchKernelGGL((k_eval<dd, N>), dim3(grid_for(n)), dim3(BLOCK), 0, s, P, z, n, I, a);
+    else hipLaunchKernelGGL((k_eval<double, N>), dim3(grid_for(n)), dim3(BLOCK), 0, s, P, z, n, I, a);
+}
+
+template <int N>
+void launch_run(const PlanDev &P, const DensityDev &D, const RunArgs &A, int grid, amm_ctx *c, hipStream_t s,
+                amm_ctx::Ev *ev) {
+    if (ev) hipEventRecord(ev->a, s);
+    hipLaunchKernelGGL((k_integrate<N>), dim3(grid), dim3(BLOCK), 0, s, P, D, A, c->d_part, c->d_flag, c->d_nflag);
+    if (ev) hipEventRecord(ev->b, s);
+    hipLaunchKernelGGL((k_dd<N>), dim3(grid), dim3(BLOCK), 0, s, P, D, A, c->d_part, c->d_flag, c->d_nflag);
+    if (ev) hipEventRecord(ev->c, s);
+}
+
+void prof_collect(amm_ctx *c) {
+    for (auto &e : c->evs) {
+        hipEventSynchronize(e.d);
+        float t1 = 0, t2 = 0, t3 = 0;
+        hipEventElapsedTime(&t1, e.a, e.b);
+        hipEventElapsedTime(&t2, e.b, e.c);
+        hipEventElapsedTime(&t3, e.c, e.d);
+        c->prof_ms[0] += t1; c->prof_ms[1] += t2; c->prof_ms[2] += t3;
+        c->prof_launch += 1;
+        c->prof_samples += e.samples;
+        hipEventDestroy(e.a); hipEventDestroy(e.b); hipEventDestroy(e.c); hipEventDestroy(e.d);
+    }
+    c->evs.clear();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *amm_last_error(void) { return g_err.c_str(); }
+
+int amm_create(amm_ctx **out, int device) {
+    if (!out) return fail(AMM_E_ARG, "amm_create: out is NULL");
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(AMM_E_ARG, "amm_create: no such device");
+    HIPCHK(hipSetDevice(device));
+    std::unique_ptr<amm_ctx> c(new amm_ctx);
+    c->device = device;
+    HIPCHK(hipMalloc((void **)&c->d_part, (size_t)MAX_CHUNKS_PER_LAUNCH * NSTAT_MAX * sizeof(double)));
+    HIPCHK(hipMalloc((void **)&c->d_flag, (size_t)MAX_CHUNKS_PER_LAUNCH * CHUNK * sizeof(uint32_t)));
+    HIPCHK(hipMalloc((void **)&c->d_nflag, (size_t)MAX_CHUNKS_PER_LAUNCH * sizeof(int32_t)));
+    *out = c.release();
+    return AMM_OK;
+}
+
+void amm_destroy(amm_ctx *ctx) { delete ctx; }
+
+int amm_enumerate(amm_ctx *c, int loops, int *n_se, int *n_vertex, int *M) {
+    if (!c) return fail(AMM_E_ARG, "amm_enumerate: ctx is NULL");
+    if (loops < 1 || loops > MAXN) return fail(AMM_E_ARG, "amm_enumerate: loops must be 1..5");
+    if (c->loops != loops) {
+        hipSetDevice(c->device);
+        for (auto &s : c->slots) {
+            hipFree(s.d_levels); hipFree(s.d_terms); hipFree(s.d_ops); hipFree(s.d_monos); hipFree(s.d_ranges);
+            hipFree(s.d_deg1); hipFree(s.d_deg3); hipFree(s.d_W1); hipFree(s.d_logdeg1);
+            hipFree(s.d_ptheta); hipFree(s.d_pilotW);
+        }
+        c->slots.clear();
+        c->graphs = enumerate_se(loops);
+        c->loops = loops;
+        c->slots.resize(c->graphs.size());
+        hipFree(c->d_acc);
+        c->d_acc = nullptr;
+        HIPCHK(hipMalloc((void **)&c->d_acc, c->graphs.size() * NSTAT_MAX * sizeof(double)));
+        HIPCHK(hipMemset(c->d_acc, 0, c->graphs.size() * NSTAT_MAX * sizeof(double)));
+    }
+    if (n_se) *n_se = (int)c->graphs.size();
+    if (n_vertex) *n_vertex = (int)c->graphs.size() * (2 * loops - 1);
+    if (M) *M = 3 * loops - 1;
+    return AMM_OK;
+}
+
+int amm_graph_desc(const amm_ctx *c, int g, int *chords, int *classes) {
+    if (!c || g < 0 || g >= (int)c->graphs.size()) return fail(AMM_E_ARG, "amm_graph_desc: bad graph");
+    const SEGraph &G = c->graphs[g];
+    if (chords)
+        for (size_t i = 0; i < G.chords.size(); ++i) { chords[2 * i] = G.chords[i].first; chords[2 * i + 1] = G.chords[i].second; }
+    if (classes)
+        for (int e = 0; e < 2 * G.n - 1; ++e) {
+            auto k = vertex_class(G, e);
+            for (int q = 0; q < 3; ++q) classes[3 * e + q] = k[q];
+        }
+    return AMM_OK;
+}
+
+int amm_build_tables(amm_ctx *c, const amm_density_params *params, int gb, int ge) {
+    if (!c || c->loops == 0) return fail(AMM_E_ARG, "amm_build_tables: call amm_enumerate first");
+    if (gb < 0 || ge > (int)c->graphs.size() || gb >= ge) return fail(AMM_E_ARG, "amm_build_tables: bad graph range");
+    if (c->loops > 4) return fail(AMM_E_TOOBIG, "amm_build_tables: integrand tables are built for 1..4 loops");
+    amm_density_params p;
+    if (params) p = *params;
+    else p = amm_density_params{0.256, 0.839, 0.786, 0.2, 0.0, 0.2, {((1.0 - 0.03) - 0.01) - 0.06, 0.03, 0.01, 0.06}, 0.75};
+    HIPCHK(hipSetDevice(c->device));
+    for (int g = gb; g < ge; ++g) {
+        GraphSlot &s = c->slots[g];
+        const SEGraph &G = c->graphs[g];
+        try {
+            build_density(G, p, s.dens);
+            build_plan(G, s.plan);
+        } catch (const std::exception &ex) {
+            return fail(AMM_E_NUMERIC, std::string("amm_build_tables: ") + ex.what());
+        }
+        s.n = G.n; s.M = 3 * G.n - 1; s.ne = 2 * G.n - 1;
+        s.uid = (uint32_t)((G.n << 20) | g);
+        // classes
+        std::vector<std::array<int, 3>> ucls;
+        for (int e = 0; e < s.ne; ++e) {
+            auto k = vertex_class(G, e);
+            int id = -1;
+            for (size_t q = 0; q < ucls.size(); ++q) if (ucls[q] == k) id = (int)q;
+            if (id < 0) { id = (int)ucls.size(); ucls.push_back(k); }
+            s.cls_of[e] = id;
+        }
+        s.ncls = (int)ucls.size();
+        for (int q = 0; q < s.ncls; ++q) for (int w = 0; w < 3; ++w) s.cls_kmm[q][w] = ucls[q][w];
+        hipFree(s.d_levels); hipFree(s.d_terms); hipFree(s.d_ops); hipFree(s.d_monos); hipFree(s.d_ranges);
+        hipFree(s.d_deg1); hipFree(s.d_deg3); hipFree(s.d_W1); hipFree(s.d_logdeg1);
+        std::vector<int2> rg(s.plan.ranges.size());
+        for (size_t i = 0; i < rg.size(); ++i) rg[i] = make_int2(s.plan.ranges[i].first, s.plan.ranges[i].second);
+        int rc;
+        if ((rc = upload(&s.d_levels, s.plan.levels.data(), s.plan.levels.size()))) return rc;
+        if ((rc = upload(&s.d_terms, s.plan.terms.data(), s.plan.terms.size()))) return rc;
+        if ((rc = upload(&s.d_ops, s.plan.ops.data(), s.plan.ops.size()))) return rc;
+        if ((rc = upload(&s.d_monos, s.plan.monos.data(), s.plan.monos.size()))) return rc;
+        if ((rc = upload(&s.d_ranges, rg.data(), rg.size()))) return rc;
+        if ((rc = upload(&s.d_deg1, s.dens.deg1.data(), s.dens.deg1.size()))) return rc;
+        if ((rc = upload(&s.d_deg3, s.dens.deg3.data(), s.dens.deg3.size()))) return rc;
+        if ((rc = upload(&s.d_W1, s.dens.W1.data(), s.dens.W1.size()))) return rc;
+        if ((rc = upload(&s.d_logdeg1, s.dens.logdeg1.data(), s.dens.logdeg1.size()))) return rc;
+        s.acc.assign(NSTAT_MAX, 0.0);
+        s.built = true;
+    }
+    return AMM_OK;
+}
+
+int amm_plan_stats(const amm_ctx *c, int g, amm_plan_info *out) {
+    if (!c || !out || g < 0 || g >= (int)c->slots.size()) return fail(AMM_E_ARG, "amm_plan_stats: bad argument");
+    const GraphSlot &s = c->slots[g];
+    if (!s.built) return fail(AMM_E_NOTBUILT, "amm_plan_stats: tables not built");
+    out->n_insertions = s.ne;
+    out->n_terms = (int)s.plan.terms.size();
+    out->n_terms_expanded = s.plan.n_terms_expanded;
+    out->n_level_evals = (int)s.plan.ops.size();
+    out->n_monomials = s.plan.n_monos_per_sample;
+    out->flops_per_sample = s.plan.flops_per_sample;
+    return AMM_OK;
+}
+
+int amm_sample(amm_ctx *c, int g, uint64_t seed, uint64_t c0, uint64_t n, double *z, double *gx, int32_t *gj,
+               int32_t *path, int32_t *comp, void *stream) {
+    if (!c || g < 0 || g >= (int)c->slots.size()) return fail(AMM_E_ARG, "amm_sample: bad graph");
+    GraphSlot &s = c->slots[g];
+    if (!s.built) return fail(AMM_E_NOTBUILT, "amm_sample: tables not built");
+    if (n == 0) return AMM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(c->device));
+    DensityDev D = s.dens_dev(false);
+    dim3 gr(grid_for(n)), bl(BLOCK);
+    switch (s.M) {
+        case 2: hipLaunchKernelGGL(k_sample<2>, gr, bl, 0, st, D, s.uid, seed, c0, n, z, gx, gj, path, comp); break;
+        case 5: hipLaunchKernelGGL(k_sample<5>, gr, bl, 0, st, D, s.uid, seed, c0, n, z, gx, gj, path, comp); break;
+        case 8: hipLaunchKernelGGL(k_sample<8>, gr, bl, 0, st, D, s.uid, seed, c0, n, z, gx, gj, path, comp); break;
+        case 11: hipLaunchKernelGGL(k_sample<11>, gr, bl, 0, st, D, s.uid, seed, c0, n, z, gx, gj, path, comp); break;
+        default: return fail(AMM_E_ARG, "amm_sample: unsupported M");
+    }
+    HIPCHK(hipGetLastError());
+    c->last_stream = st;
+    return AMM_OK;
+}
+
+int amm_eval(amm_ctx *c, int g, const double *z, uint64_t n, double *I, double *absI, int precision, void *stream) {
+    if (!c || g < 0 || g >= (int)c->slots.size()) return fail(AMM_E_ARG, "amm_eval: bad argument");
+    GraphSlot &s = c->slots[g];
+    if (!s.built) return fail(AMM_E_NOTBUILT, "amm_eval: tables not built");
+    if (n == 0) return AMM_OK;
+    if (!z) return fail(AMM_E_ARG, "amm_eval: z is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(c->device));
+    PlanDev P = s.plan_dev();
+    switch (s.n) {
+        case 1: launch_eval<1>(P, z, n, I, absI, precision, st); break;
+        case 2: launch_eval<2>(P, z, n, I, absI, precision, st); break;
+        case 3: launch_eval<3>(P, z, n, I, absI, precision, st); break;
+        case 4: launch_eval<4>(P, z, n, I, absI, precision, st); break;
+        default: return fail(AMM_E_ARG, "amm_eval: unsupported loop order");
+    }
+    HIPCHK(hipGetLastError());
+    c->last_stream = st;
+    return AMM_OK;
+}
+
+int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
+    if (!c || !r) return fail(AMM_E_ARG, "amm_integrate: bad argument");
+    if (r->graph_begin < 0 || r->graph_end > (int)c->slots.size() || r->graph_begin >= r->graph_end)
+        return fail(AMM_E_ARG, "amm_integrate: bad graph range");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(c->device));
+    int dev_cus = 256;
+    hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    for (int g = r->graph_begin; g < r->graph_end; ++g) {
+        GraphSlot &s = c->slots[g];
+        if (!s.built) return fail(AMM_E_NOTBUILT, "amm_integrate: tables not built");
+        if (!r->accumulate)
+            hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, c->d_acc + (size_t)g * NSTAT_MAX, NSTAT_MAX);
+        bool learned = r->sampler == 1 && s.d_ptheta != nullptr;
+        PlanDev P = s.plan_dev();
+        DensityDev D = s.dens_dev(learned);
+        RunArgs A;
+        A.seed = r->seed;
+        A.begin = r->counter0;
+        A.end = r->counter0 + r->n_per_graph;
+        A.uid = s.uid;
+        A.ncls = s.ncls;
+        for (int e = 0; e < MAXNE; ++e) A.cls_of[e] = e < s.ne ? s.cls_of[e] : 0;
+        A.learned = learned ? 1 : 0;
+        if (r->force_flag) A.tau = -1.0;
+        else if (r->accept_tau) A.tau = r->accept_tau[g - r->graph_begin];
+        else A.tau = INFINITY;
+        uint64_t nchunks_total = (r->n_per_graph + CHUNK - 1) / CHUNK;
+        int grid_target = r->samples_per_thread > 0 ? r->samples_per_thread * dev_cus : 8 * dev_cus;
+        for (uint64_t ch0 = 0; ch0 < nchunks_total; ch0 += MAX_CHUNKS_PER_LAUNCH) {
+            int nch = (int)std::min<uint64_t>(MAX_CHUNKS_PER_LAUNCH, nchunks_total - ch0);
+            A.chunk0 = (int)ch0;
+            A.nchunks = nch;
+            int grid = std::min(nch, grid_target);
+            amm_ctx::Ev ev, *evp = nullptr;
+            if (c->prof) {
+                HIPCHK(hipEventCreate(&ev.a)); HIPCHK(hipEventCreate(&ev.b));
+                HIPCHK(hipEventCreate(&ev.c)); HIPCHK(hipEventCreate(&ev.d));
+                uint64_t lo = ch0 * CHUNK, hi = std::min<uint64_t>((ch0 + nch) * CHUNK, r->n_per_graph);
+                ev.samples = (int64_t)(hi - lo);
+                evp = &ev;
+            }
+            switch (s.n) {
+                case 1: launch_run<1>(P, D, A, grid, c, st, evp); break;
+                case 2: launch_run<2>(P, D, A, grid, c, st, evp); break;
+                case 3: launch_run<3>(P, D, A, grid, c, st, evp); break;
+                case 4: launch_run<4>(P, D, A, grid, c, st, evp); break;
+                default: return fail(AMM_E_ARG, "amm_integrate: unsupported loop order");
+            }
+            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, st, c->d_part, nch, s.nstat(),
+                               c->d_acc + (size_t)g * NSTAT_MAX);
+            if (evp) {
+                HIPCHK(hipEventRecord(ev.d, st));
+                c->evs.push_back(ev);
+            }
+        }
+        HIPCHK(hipGetLastError());
+    }
+    c->last_stream = st;
+    return AMM_OK;
+}
+
+int amm_profile(amm_ctx *c, int enable, double *ms_fp64, double *ms_dd, double *ms_reduce, int64_t *n_launches,
+                int64_t *n_samples) {
+    if (!c) return fail(AMM_E_ARG, "amm_profile: ctx is NULL");
+    HIPCHK(hipSetDevice(c->device));
+    prof_collect(c);
+    if (ms_fp64) *ms_fp64 = c->prof_ms[0];
+    if (ms_dd) *ms_dd = c->prof_ms[1];
+    if (ms_reduce) *ms_reduce = c->prof_ms[2];
+    if (n_launches) *n_launches = c->prof_launch;
+    if (n_samples) *n_samples = c->prof_samples;
+    if (enable && !c->prof) {
+        c->prof_ms[0] = c->prof_ms[1] = c->prof_ms[2] = 0;
+        c->prof_launch = c->prof_samples = 0;
+    }
+    c->prof = enable != 0;
+    return AMM_OK;
+}
+
+int amm_read(amm_ctx *c, int g, int e, int ck, int cm, int cmp, amm_estimate *out) {
+    if (!c || !out) return fail(AMM_E_ARG, "amm_read: bad argument");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->last_stream));
+    std::vector<double> all(c->slots.size() * NSTAT_MAX);
+    if (!all.empty())
+        HIPCHK(hipMemcpy(all.data(), c->d_acc, all.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof(*out));
+    auto fin = [&](double s, double s2, double n) {
+        out->mean = n > 0 ? s / n : 0.0;
+        double var = n > 0 ? s2 / (n * n) - s * s / (n * n * n) : 0.0;
+        out->sigma = std::sqrt(var > 0 ? var : 0.0);
+    };
+    if (g >= 0) {
+        if (g >= (int)c->slots.size() || !c->slots[g].built) return fail(AMM_E_ARG, "amm_read: graph not built");
+        const GraphSlot &s = c->slots[g];
+        const double *a = &all[(size_t)g * NSTAT_MAX];
+        int ne = s.ne, nst = s.nstat();
+        out->n = (uint64_t)a[nst - 4];
+        out->n_flag = (uint64_t)a[nst - 3];
+        out->n_dd_fail = (uint64_t)a[nst - 2];
+        out->n_ood = (uint64_t)a[nst - 1];
+        if (e >= 0) {
+            if (e >= ne) return fail(AMM_E_ARG, "amm_read: bad insertion");
+            out->sum_y = a[e]; out->sum_y2 = a[ne + e]; out->sum_abs = a[2 * ne + e];
+            fin(out->sum_y, out->sum_y2, (double)out->n);
+        } else {
+            // sum over insertions: classes carry the covariance
+            double s1 = 0, s2 = 0, sa = 0;
+            for (int q = 0; q < s.ncls; ++q) { s1 += a[3 * ne + q]; }
+            for (int q = 0; q < ne; ++q) sa += a[2 * ne + q];
+            // variance of the sum: add class variances (classes are sums at the same point)
+            double n = (double)out->n, var = 0;
+            for (int q = 0; q < s.ncls; ++q) {
+                double cs = a[3 * ne + q], cs2 = a[3 * ne + s.ncls + q];
+                var += n > 0 ? cs2 / (n * n) - cs * cs / (n * n * n) : 0.0;
+            }
+            out->sum_y = s1; out->sum_abs = sa;
+            out->mean = n > 0 ? s1 / n : 0.0;
+            out->sigma = std::sqrt(var > 0 ? var : 0.0);
+            (void)s2;
+        }
+        return AMM_OK;
+    }
+    // class over all built graphs: means add, sigma^2 add (eq. sigma_sum)
+    double mean = 0, var = 0;
+    uint64_t ntot = 0, nfl = 0, ndd = 0, nood = 0;
+    for (size_t gi = 0; gi < c->slots.size(); ++gi) {
+        const GraphSlot &s = c->slots[gi];
+        if (!s.built) continue;
+        const double *a = &all[gi * NSTAT_MAX];
+        int ne = s.ne, nst = s.nstat();
+        double n = a[nst - 4];
+        for (int q = 0; q < s.ncls; ++q) {
+            if (ck >= 0 && (s.cls_kmm[q][0] != ck || s.cls_kmm[q][1] != cm || s.cls_kmm[q][2] != cmp)) continue;
+            double cs = a[3 * ne + q], cs2 = a[3 * ne + s.ncls + q];
+            if (n > 0) {
+                mean += cs / n;
+                double v = cs2 / (n * n) - cs * cs / (n * n * n);
+                var += v > 0 ? v : 0;
+            }
+        }
+        ntot += (uint64_t)n; nfl += (uint64_t)a[nst - 3]; ndd += (uint64_t)a[nst - 2]; nood += (uint64_t)a[nst - 1];
+    }
+    out->mean = mean; out->sigma = std::sqrt(var);
+    out->n = ntot; out->n_flag = nfl; out->n_dd_fail = ndd; out->n_ood = nood;
+    return AMM_OK;
+}
+
+}  // extern "C"
