@@ -62,6 +62,7 @@ def main():
     ap.add_argument('--steps', type=int, default=5)
     ap.add_argument('--warmup', type=int, default=1)
     ap.add_argument('--batch', type=int, default=1 << 22, help='sample counters per graph per step')
+    ap.add_argument('--pilot', type=int, default=100_000, help='double-double pilot samples per graph')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) != 1:
@@ -79,15 +80,23 @@ def main():
     flops = [ctx.plan_stats(g)['flops_per_sample'] for g in range(G)]
     stream = torch.cuda.current_stream()
     B = args.batch
+    # pilot (every point in double-double, seed 1) -> round-off acceptance
+    # thresholds of eq. (interval_accept) for the full 1e9-sample run
+    ctx.integrate(seed=1, n_per_graph=args.pilot, force_flag=1)
+    tau = ctx.accept_thresholds(1_000_000_000)
     counter = 0
+    first = True
     for _ in range(args.warmup):
-        ctx.integrate(seed=0, n_per_graph=B, counter0=counter, accumulate=1)
+        ctx.integrate(seed=0, n_per_graph=B, counter0=counter, accumulate=0 if first else 1, accept_tau=tau)
+        first = False
         counter += B
     torch.cuda.synchronize()
     ctx.profile(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.integrate(seed=0, n_per_graph=B, counter0=counter, accumulate=1, stream=stream)
+        ctx.integrate(seed=0, n_per_graph=B, counter0=counter, accumulate=0 if first else 1, accept_tau=tau,
+                      stream=stream)
+        first = False
         counter += B
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -117,7 +126,9 @@ def main():
                      "kernel_launches": prof['launches'],
                      "flops_per_sample": {str(g): flops[g] for g in range(G)}},
         "phase_ms": {"fp64": prof['ms_fp64'], "dd": prof['ms_dd'], "reduce": prof['ms_reduce']},
-        "estimate_3loop_so_far": {"mean": est['mean'], "sigma": est['sigma'], "n_ood": est['n_ood']},
+        "estimate_3loop_so_far": {"mean": est['mean'], "sigma": est['sigma'], "n": est['n'],
+                                  "n_flag": est['n_flag'], "n_dd_fail": est['n_dd_fail'], "n_ood": est['n_ood']},
+        "flag_rate": est['n_flag'] / max(est['n'], 1),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -117,24 +117,35 @@ int amm_build_tables(amm_ctx *ctx, const amm_density_params *params,
 /* Static plan statistics of graph g (after amm_build_tables). */
 int amm_plan_stats(const amm_ctx *ctx, int g, amm_plan_info *out);
 
-/* Sample n points of graph g: sample indices counter0..counter0+n-1.
+/* Sample n points of graph g: sample indices counter0..counter0+n-1; learned
+ * = 1 draws from the learned mixture (needs a sector table; component 4 =
+ * q_theta).
  * Device outputs (any may be NULL): z [n x M] doubles, gx [n] mantissa and
  * gj [n] int32 exponent of g = gx 2^gj (Sec. IV.A), path [n x M] int32 line
  * order z_{path0} >= z_{path1} >= ..., comp [n] int32 mixture component. */
 int amm_sample(amm_ctx *ctx, int g, uint64_t seed, uint64_t counter0, uint64_t n,
-               double *z, double *gx, int32_t *gj, int32_t *path, int32_t *comp,
+               int learned, double *z, double *gx, int32_t *gj, int32_t *path, int32_t *comp,
                void *stream);
 
 /* Evaluate the integrands of all 2n-1 insertions of graph g at n device
- * points z [n x M]: I [n x (2n-1)] and the sum of |term| per insertion
- * absI [n x (2n-1)] (either may be NULL).  precision: 0 = FP64,
- * 1 = double-double (value rounded to double). */
+ * points z [n x M]: I [n x (2n-1)], the sum of |term| per insertion
+ * absI [n x (2n-1)] and (FP64 only) the round-off bound of I, bound
+ * [n x (2n-1)], from the propagated operation magnitudes (any output may be
+ * NULL).  precision: 0 = FP64, 1 = double-double (value rounded to double). */
 int amm_eval(amm_ctx *ctx, int g, const double *z, uint64_t n,
-             double *I, double *absI, int precision, void *stream);
+             double *I, double *absI, double *bound, int precision, void *stream);
 
 /* Run the Monte Carlo (sample, evaluate, round-off check, double-double
  * recompute of flagged points, accumulate) asynchronously on `stream`. */
 int amm_integrate(amm_ctx *ctx, const amm_run_params *run, void *stream);
+
+/* Round-off acceptance thresholds of eq. (interval_accept), Sec. IV.A:
+ * tau_j = (1/4) sigma_j sqrt(sum_l sigma_l^2) / sum_l sigma_l over the graphs
+ * [graph_begin, graph_end), where sigma_j is the current accumulators'
+ * sigma of graph j (all insertions summed; a pilot run) scaled to a run of
+ * n_run samples: sigma_j sqrt(N_pilot / n_run).  Writes graph_end -
+ * graph_begin doubles to the host array tau (to pass as accept_tau). */
+int amm_accept_thresholds(amm_ctx *ctx, int graph_begin, int graph_end, uint64_t n_run, double *tau);
 
 /* Read accumulators (synchronises the last stream used).  g >= 0 selects a
  * graph; e >= 0 an insertion of it, e = -1 the sum over its insertions.
@@ -174,13 +185,19 @@ int amm_mlp_set_params(amm_ctx *ctx, const float *host, size_t count);
  * row r corresponds to (s = mask_of_row[r], j = line_of_row[r]). */
 int amm_mlp_features(const amm_ctx *ctx, int g, float *rows, int32_t *mask_of_row,
                      int32_t *line_of_row, size_t cap, size_t *n_rows);
-/* One forward+backward pass of the MLP loss on device rows (for gradient
- * checks): rows [n x 16], row weights w [n], group id of each row grp [n]
- * (rows of one (graph, s) group form one softmax), prior log-probabilities
- * lp0 [n]; outputs loss (device, 1 float) and gradient (device, count floats). */
-int amm_mlp_loss_grad(amm_ctx *ctx, const float *rows, const float *w, const int32_t *grp,
-                      const float *lp0, int n_rows, int n_groups, float *loss, float *grad,
-                      void *stream);
+/* Loss and gradient of the MLP objective on device rows (for gradient
+ * checks): rows [n_rows x 16] features (feature 0 = log of the plain sector
+ * probability), w [n_rows] row weights, goff [n_groups+1] offsets of the
+ * softmax groups (rows of one set s are contiguous).  Outputs: loss (device,
+ * 1 float) and grad (device, count floats).  Uses the current parameters
+ * (amm_mlp_set_params).  Synchronises `stream`. */
+int amm_mlp_loss_grad(amm_ctx *ctx, const float *rows, const float *w, const int32_t *goff,
+                      int n_rows, int n_groups, float *loss, float *grad, void *stream);
+/* Install a sector table P(j | s) for graph g from host memory
+ * ([2^M x M] floats; row s holds the weights of the lines j in s; they are
+ * normalised over j in s when used).  NULL removes the table.  Sampling with
+ * the learned mixture (sampler = 1) then uses this table. */
+int amm_set_sector_table(amm_ctx *ctx, int g, const float *host_table);
 
 #ifdef __cplusplus
 }

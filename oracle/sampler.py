@@ -134,9 +134,14 @@ class Density:
         # log K_c (path-independent part)
         self.logK = [-logF1, -logM, float(M - 1) * logD - logF1, -logMfact]
 
-    def sample(self, u):
-        """u: (N, 2M-1) uniforms.  Returns dict with z (N, M), path (N, M),
-        and the density as (x, j) with g = x 2^j."""
+    def sample(self, u, ptheta=None):
+        """u: (N, 2M-1) uniforms (2M with a learned table).  Returns dict with
+        z (N, M), path (N, M), and the density as (x, j) with g = x 2^j.
+
+        With ptheta (P_theta(j|s) as a [2^M, M] float32 table) the density is
+        the learned mixture q = (q_theta + g)/2: uniform 2M-1 picks q_theta
+        (component 4) when below 1/2; q_theta chooses sectors by the table and
+        shares g1's continuous part."""
         M = self.M
         N = u.shape[0]
         comp = np.zeros(N, dtype=np.int64)
@@ -150,6 +155,9 @@ class Density:
             take = (~chosen) & (thr < cum)
             comp[take] = ci
             chosen |= take
+        if ptheta is not None:
+            P = np.asarray(ptheta, dtype=np.float32).astype(np.float64)
+            comp[u[:, 2 * M - 1] < 0.5] = 4
         path = np.zeros((N, M), dtype=np.int64)
         s = np.full(N, self.full, dtype=np.int64)
         uniform_sel = (comp == 1) | (comp == 3)
@@ -186,6 +194,24 @@ class Density:
                 upick[hit] = j
                 cnt += inset
             pick = np.where(uniform_sel, upick, pick)
+            if ptheta is not None:
+                # table choice for component 4
+                ttot = np.zeros(N)
+                for j in range(M):
+                    inset = ((s >> j) & 1).astype(bool)
+                    ttot = ttot + np.where(inset, P[s, j], 0.0)
+                tt = ul * ttot
+                cumw = np.zeros(N)
+                tpick = np.full(N, -1, dtype=np.int64)
+                tlast = np.full(N, -1, dtype=np.int64)
+                for j in range(M):
+                    inset = ((s >> j) & 1).astype(bool)
+                    cumw = cumw + np.where(inset, P[s, j], 0.0)
+                    hit = inset & (tpick < 0) & (tt < cumw)
+                    tpick[hit] = j
+                    tlast[inset] = j
+                tpick = np.where(tpick < 0, tlast, tpick)
+                pick = np.where(comp == 4, tpick, pick)
             path[:, l] = pick
             s = s & ~(np.int64(1) << pick)
         # last line
@@ -206,7 +232,7 @@ class Density:
             size = np.zeros(N)
             for j in range(M):
                 size = size + ((sl >> j) & 1)
-            dsel = np.where(comp == 0, d1, np.where(comp == 1, size, np.where(comp == 2, self.deg3[sl], d1)))
+            dsel = np.where(comp == 1, size, np.where(comp == 2, self.deg3[sl], d1))
             logt[:, l] = amm_log(u[:, M + l - 1]) / dsel
         tt = amm_exp(logt)
         p = np.ones((N, M))
@@ -242,9 +268,24 @@ class Density:
         for ci in range(4):
             Lc[ci] = (self.logc[ci] + self.logK[ci]) + E[ci]
         Lc[3] = Lc[3] + logdegsum
+        ncomp = 4
+        if ptheta is not None:
+            loghalf = float(amm_log(0.5))
+            sumlogp = np.zeros(N)
+            for l in range(M - 1):
+                sl = masks[:, l]
+                tot = np.zeros(N)
+                for j in range(M):
+                    tot = tot + np.where(((sl >> j) & 1).astype(bool), P[sl, j], 0.0)
+                sumlogp = sumlogp + amm_log(P[sl, path[:, l]] / tot)
+            Lt = ((loghalf + sumlogp) + logdegsum) + E[0]
+            Lc = np.vstack([Lc + loghalf, Lt[None, :]])
+            ncomp = 5
         Lmax = np.maximum(np.maximum(Lc[0], Lc[1]), np.maximum(Lc[2], Lc[3]))
+        if ncomp == 5:
+            Lmax = np.maximum(Lmax, Lc[4])
         S = np.zeros(N)
-        for ci in range(4):
+        for ci in range(ncomp):
             S = S + amm_exp(Lc[ci] - Lmax)
         Ltot = Lmax - sumlogz
         k = np.rint(Ltot * INV_LN2)
@@ -255,13 +296,13 @@ class Density:
         return dict(z=z, path=path, comp=comp, gx=xm, gj=j, logt=logt)
 
 
-def sample_graph(n, gi, seed, start, count, dens=None, params=CALC2):
+def sample_graph(n, gi, seed, start, count, dens=None, params=CALC2, ptheta=None):
     chords = G.se_graphs(n)[gi]
     if dens is None:
         dens = Density(n, chords, params)
     idx = np.arange(start, start + count, dtype=np.uint64)
-    u = uniforms(seed, graph_uid(n, gi), idx, 2 * dens.M - 1)
-    out = dens.sample(u)
+    u = uniforms(seed, graph_uid(n, gi), idx, 2 * dens.M - (1 if ptheta is None else 0))
+    out = dens.sample(u, ptheta)
     out['u'] = u
     return out, dens
 

@@ -55,12 +55,13 @@ SYMBOLS = {
     'amm_graph_desc': (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     'amm_build_tables': (C.c_int, [C.c_void_p, C.POINTER(DensityParams), C.c_int, C.c_int]),
     'amm_plan_stats': (C.c_int, [C.c_void_p, C.c_int, C.POINTER(PlanInfo)]),
-    'amm_sample': (C.c_int, [C.c_void_p, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p,
-                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
-    'amm_eval': (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_int,
-                           C.c_void_p]),
+    'amm_sample': (C.c_int, [C.c_void_p, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int, C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    'amm_eval': (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p,
+                           C.c_int, C.c_void_p]),
     'amm_integrate': (C.c_int, [C.c_void_p, C.POINTER(RunParams), C.c_void_p]),
     'amm_read': (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Estimate)]),
+    'amm_accept_thresholds': (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_uint64, C.c_void_p]),
     'amm_profile': (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                               C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     'amm_pilot': (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64, C.c_int, C.c_int, C.c_void_p]),
@@ -69,8 +70,9 @@ SYMBOLS = {
     'amm_mlp_set_params': (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     'amm_mlp_features': (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                    C.POINTER(C.c_size_t)]),
-    'amm_mlp_loss_grad': (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
-                                    C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    'amm_mlp_loss_grad': (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]),
+    'amm_set_sector_table': (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
 }
 
 
@@ -158,7 +160,7 @@ class Context:
         _check(lib().amm_plan_stats(self.h, g, C.byref(s)), 'amm_plan_stats')
         return {k: getattr(s, k) for k, _ in s._fields_}
 
-    def sample(self, g, seed, counter0, n, stream=None):
+    def sample(self, g, seed, counter0, n, learned=0, stream=None):
         import torch
         dev = f'cuda:{self.device}'
         M = self.M
@@ -167,19 +169,21 @@ class Context:
         gj = torch.empty(n, dtype=torch.int32, device=dev)
         path = torch.empty((n, M), dtype=torch.int32, device=dev)
         comp = torch.empty(n, dtype=torch.int32, device=dev)
-        _check(lib().amm_sample(self.h, g, seed, counter0, n, _ptr(z), _ptr(gx), _ptr(gj), _ptr(path),
-                                _ptr(comp), _stream(stream)), 'amm_sample')
+        _check(lib().amm_sample(self.h, g, seed, counter0, n, int(learned), _ptr(z), _ptr(gx), _ptr(gj),
+                                _ptr(path), _ptr(comp), _stream(stream)), 'amm_sample')
         return dict(z=z, gx=gx, gj=gj, path=path, comp=comp)
 
-    def eval(self, g, z, precision=0, stream=None):
+    def eval(self, g, z, precision=0, with_bound=False, stream=None):
         import torch
         n = z.shape[0]
         ne = 2 * self.loops - 1
         I = torch.empty((n, ne), dtype=torch.float64, device=z.device)
         A = torch.empty((n, ne), dtype=torch.float64, device=z.device)
+        B = torch.empty((n, ne), dtype=torch.float64, device=z.device) if with_bound else None
         zc = z.contiguous()
-        _check(lib().amm_eval(self.h, g, _ptr(zc), n, _ptr(I), _ptr(A), precision, _stream(stream)), 'amm_eval')
-        return I, A
+        _check(lib().amm_eval(self.h, g, _ptr(zc), n, _ptr(I), _ptr(A), _ptr(B), precision, _stream(stream)),
+               'amm_eval')
+        return (I, A, B) if with_bound else (I, A)
 
     def integrate(self, seed, n_per_graph, graph_begin=0, graph_end=None, counter0=0, sampler=0,
                   force_flag=0, samples_per_thread=0, accumulate=0, accept_tau=None, stream=None):
@@ -192,12 +196,69 @@ class Context:
                        C.cast(tau, C.POINTER(C.c_double)) if tau is not None else None)
         _check(lib().amm_integrate(self.h, C.byref(rp), _stream(stream)), 'amm_integrate')
 
+    def accept_thresholds(self, n_run, graph_begin=0, graph_end=None):
+        graph_end = self.n_se if graph_end is None else graph_end
+        tau = (C.c_double * (graph_end - graph_begin))()
+        _check(lib().amm_accept_thresholds(self.h, graph_begin, graph_end, n_run, tau), 'amm_accept_thresholds')
+        return list(tau)
+
     def profile(self, enable):
         a, b, c = C.c_double(), C.c_double(), C.c_double()
         n, s = C.c_int64(), C.c_int64()
         _check(lib().amm_profile(self.h, int(enable), C.byref(a), C.byref(b), C.byref(c), C.byref(n), C.byref(s)),
                'amm_profile')
         return dict(ms_fp64=a.value, ms_dd=b.value, ms_reduce=c.value, launches=n.value, samples=s.value)
+
+    # ----- learned sector sampler -----
+    def pilot(self, seed, n_per_graph, graph_begin=0, graph_end=None, stream=None):
+        graph_end = self.n_se if graph_end is None else graph_end
+        _check(lib().amm_pilot(self.h, seed, n_per_graph, graph_begin, graph_end, _stream(stream)), 'amm_pilot')
+
+    def mlp_train(self, epochs, lr=1e-2, init_seed=0, stream=None):
+        _check(lib().amm_mlp_train(self.h, epochs, lr, init_seed, _stream(stream)), 'amm_mlp_train')
+
+    def mlp_params(self):
+        import numpy as np
+        cnt = C.c_size_t()
+        _check(lib().amm_mlp_params(self.h, None, 0, C.byref(cnt)), 'amm_mlp_params')
+        buf = np.empty(cnt.value, dtype=np.float32)
+        _check(lib().amm_mlp_params(self.h, buf.ctypes.data_as(C.c_void_p), cnt.value, C.byref(cnt)),
+               'amm_mlp_params')
+        return buf
+
+    def mlp_set_params(self, p):
+        import numpy as np
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(lib().amm_mlp_set_params(self.h, p.ctypes.data_as(C.c_void_p), p.size), 'amm_mlp_set_params')
+
+    def mlp_features(self, g):
+        import numpy as np
+        n = C.c_size_t()
+        _check(lib().amm_mlp_features(self.h, g, None, None, None, 0, C.byref(n)), 'amm_mlp_features')
+        rows = np.empty((n.value, 16), dtype=np.float32)
+        s = np.empty(n.value, dtype=np.int32)
+        j = np.empty(n.value, dtype=np.int32)
+        _check(lib().amm_mlp_features(self.h, g, rows.ctypes.data_as(C.c_void_p), s.ctypes.data_as(C.c_void_p),
+                                      j.ctypes.data_as(C.c_void_p), n.value, C.byref(n)), 'amm_mlp_features')
+        return rows, s, j
+
+    def mlp_loss_grad(self, rows, w, goff, stream=None):
+        import torch
+        n = rows.shape[0]
+        loss = torch.empty(1, dtype=torch.float32, device=rows.device)
+        grad = torch.empty(len(self.mlp_params()), dtype=torch.float32, device=rows.device)
+        _check(lib().amm_mlp_loss_grad(self.h, _ptr(rows.contiguous()), _ptr(w.contiguous()), _ptr(goff.contiguous()),
+                                       n, goff.shape[0] - 1, _ptr(loss), _ptr(grad), _stream(stream)),
+               'amm_mlp_loss_grad')
+        return loss, grad
+
+    def set_sector_table(self, g, table):
+        import numpy as np
+        if table is None:
+            _check(lib().amm_set_sector_table(self.h, g, None), 'amm_set_sector_table')
+            return
+        t = np.ascontiguousarray(table, dtype=np.float32)
+        _check(lib().amm_set_sector_table(self.h, g, t.ctypes.data_as(C.c_void_p)), 'amm_set_sector_table')
 
     def read(self, g=-1, e=-1, cls=None):
         est = Estimate()

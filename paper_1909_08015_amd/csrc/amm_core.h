@@ -75,6 +75,44 @@ AMM_HDI double mul_add(double a, double b, double c) { return fma(a, b, c); }
 AMM_HDI dd mul_add(dd a, dd b, dd c) { return a * b + c; }
 
 // ---------------------------------------------------------------------------
+// FP64 value with a running round-off magnitude (reading R11, in the spirit
+// of the paper's "eliminated interval arithmetic": operations on centres and
+// a cheap radius formula).  a >= |v| is the value of the same computation
+// done on magnitudes, extended through divisions by first-order error
+// propagation; the rounding error of v is bounded by ~k u a for an
+// operation-chain depth k.
+// ---------------------------------------------------------------------------
+struct ea {
+    double v, a;
+    AMM_HDI ea() : v(0), a(0) {}
+    AMM_HDI ea(double x) : v(x), a(fabs(x)) {}
+    AMM_HDI ea(double x, double m) : v(x), a(m) {}
+};
+AMM_HDI ea operator+(ea x, ea y) { return ea(x.v + y.v, x.a + y.a); }
+AMM_HDI ea operator-(ea x) { return ea(-x.v, x.a); }
+AMM_HDI ea operator-(ea x, ea y) { return ea(x.v - y.v, x.a + y.a); }
+AMM_HDI ea operator*(ea x, ea y) { return ea(x.v * y.v, x.a * y.a); }
+AMM_HDI ea operator/(ea x, ea y) {
+    double q = x.v / y.v, ay = fabs(y.v);
+    return ea(q, (x.a + fabs(q) * y.a) / ay);
+}
+AMM_HDI ea &operator+=(ea &x, ea y) { x = x + y; return x; }
+AMM_HDI ea &operator-=(ea &x, ea y) { x = x - y; return x; }
+AMM_HDI ea &operator*=(ea &x, ea y) { x = x * y; return x; }
+AMM_HDI double to_double(ea x) { return x.v; }
+AMM_HDI ea absd(ea x) { return ea(fabs(x.v), x.a); }
+AMM_HDI ea mul_add(ea x, ea y, ea z) { return ea(fma(x.v, y.v, z.v), fma(x.a, y.a, z.a)); }
+AMM_HDI double mag(ea x) { return x.a; }
+// Drop the accumulated magnitude (treat as exact): used for the outputs of
+// the backward-stable LDL^T factorisation and solves, whose relative errors
+// stay at a few u; cancellation is tracked from the dot products onwards.
+AMM_HDI ea strip(ea x) { return ea(x.v); }
+AMM_HDI double strip(double x) { return x; }
+AMM_HDI dd strip(dd x) { return x; }
+AMM_HDI double mag(double x) { return fabs(x); }
+AMM_HDI double mag(dd x) { return fabs(x.hi); }
+
+// ---------------------------------------------------------------------------
 // exp / log with the fixed operation order (no contraction): Cody-Waite
 // reduction + degree-13 Taylor polynomial; atanh series for log.
 // ---------------------------------------------------------------------------
@@ -158,6 +196,7 @@ template <int M>
 AMM_HDI SampleOut sample_point(const DensityDev &D, const double *u, double *z, int *path) {
     SampleOut o;
     const uint32_t full = (1u << M) - 1u;
+    const float *P = D.ptheta;    // learned mixture when non-null: u has 2M entries
     // mixture component
     double thr = u[0], cum = 0.0;
     int comp = 3;
@@ -166,13 +205,29 @@ AMM_HDI SampleOut sample_point(const DensityDev &D, const double *u, double *z, 
         cum = cum + D.c[ci];
         if (!chosen && thr < cum) { comp = ci; chosen = true; }
     }
+    if (P && u[2 * M - 1] < 0.5) comp = 4;
     o.comp = comp;
     bool uni = (comp == 1) || (comp == 3);
     uint32_t s = full;
     for (int l = 0; l < M - 1; ++l) {
         double ul = u[1 + l];
         int pick;
-        if (!uni) {
+        if (comp == 4) {
+            double total = 0.0;
+            for (int j = 0; j < M; ++j)
+                if ((s >> j) & 1u) total = total + (double)P[s * M + j];
+            double t = ul * total;
+            double cw = 0.0;
+            pick = -1;
+            int last = -1;
+            for (int j = 0; j < M; ++j) {
+                if (!((s >> j) & 1u)) continue;
+                cw = cw + (double)P[s * M + j];
+                if (pick < 0 && t < cw) pick = j;
+                last = j;
+            }
+            if (pick < 0) pick = last;
+        } else if (!uni) {
             double total = 0.0;
             for (int j = 0; j < M; ++j)
                 if ((s >> j) & 1u) total = total + D.W1[s & ~(1u << j)];
@@ -250,11 +305,29 @@ AMM_HDI SampleOut sample_point(const DensityDev &D, const double *u, double *z, 
     Lc[1] = (D.logc[1] + D.logK[1]) + E1;
     Lc[2] = (D.logc[2] + D.logK[2]) + E2;
     Lc[3] = ((D.logc[3] + D.logK[3]) + E0) + lds;
+    double L4 = -INFINITY;
+    int ncomp = 4;
+    if (P) {
+        const double loghalf = amm_log(0.5);
+        double sumlogp = 0.0;
+        for (int l = 0; l < M - 1; ++l) {
+            uint32_t sl = masks[l];
+            double tot = 0.0;
+            for (int j = 0; j < M; ++j)
+                if ((sl >> j) & 1u) tot = tot + (double)P[sl * M + j];
+            sumlogp = sumlogp + amm_log((double)P[sl * M + path[l]] / tot);
+        }
+        L4 = ((loghalf + sumlogp) + lds) + E0;
+        for (int ci = 0; ci < 4; ++ci) Lc[ci] = Lc[ci] + loghalf;
+        ncomp = 5;
+    }
     double a = Lc[0] > Lc[1] ? Lc[0] : Lc[1];
     double b = Lc[2] > Lc[3] ? Lc[2] : Lc[3];
     double Lmax = a > b ? a : b;
+    if (ncomp == 5) Lmax = Lmax > L4 ? Lmax : L4;
     double S = 0.0;
     for (int ci = 0; ci < 4; ++ci) S = S + amm_exp(Lc[ci] - Lmax);
+    if (ncomp == 5) S = S + amm_exp(L4 - Lmax);
     double Ltot = Lmax - sumlogz;
     double k = rint(Ltot * AMM_INV_LN2);
     double r = (Ltot - k * AMM_LN2_HI) - k * AMM_LN2_LO;
@@ -298,123 +371,199 @@ AMM_HDI void conv_into(const T *a, const T *b, T *out) {
     }
 }
 
-// Evaluate one level: returns c-vectors per output (out[o][c]) given the
-// children's values on the stack.  Adds the level's V to vtot.
-template <typename T, int N>
-AMM_HDI void eval_level(const PlanDev &P, const LevelDesc &d, const double *z,
-                        T (*stk)[2][N], int &sp, T &vtot) {
+// Storage of a level's polynomial variables.  VarsPriv keeps them in a
+// private array (double-double path); VarsLds keeps one LDS column per thread
+// (address base + i * stride, conflict-free for wave-uniform i).  For the
+// magnitude type only the values are stored; the magnitude of a variable is
+// |v| times the level's largest magnitude/value ratio.
+template <typename T, int NV> struct VarsPriv {
+    T v[NV];
+    AMM_HDI void begin() {}
+    AMM_HDI void set(int i, const T &x) { v[i] = x; }
+    AMM_HDI T get(int i) const { return v[i]; }
+};
+struct VarsLdsD {
+    double *base;
+    int stride;
+    AMM_HDI void begin() {}
+    AMM_HDI void set(int i, double x) { base[i * stride] = x; }
+    AMM_HDI double get(int i) const { return base[i * stride]; }
+};
+struct VarsLdsEa {
+    double *base;      // values
+    float *rbase;      // magnitude / |value| per variable
+    int stride;
+    AMM_HDI void begin() {}
+    AMM_HDI void set(int i, const ea &x) {
+        base[i * stride] = x.v;
+        double ax = fabs(x.v);
+        rbase[i * stride] = ax > 0.0 ? (float)(x.a / ax) : (x.a > 0.0 ? INFINITY : 1.0f);
+    }
+    AMM_HDI ea get(int i) const {
+        double v = base[i * stride];
+        return ea(v, fabs(v) * (double)rbase[i * stride]);
+    }
+};
+
+// Evaluate one level: c-vectors per output (pushed on the value stack) given
+// the children's values on the stack.  Adds the level's V to vtot.
+template <typename T, int N, typename Vars>
+AMM_HDI void eval_level(const PlanDev &P, const LevelDesc &d, const double *z, T (*stk)[2][N], int &sp, T &vtot,
+                        Vars &vars) {
     constexpr int KM = Dims<N>::KM;
     const int K = d.K, L = d.L;
     T zseg[KM + 1], zph[N];
+#pragma unroll
     for (int k = 1; k <= KM; ++k) {
-        if (k > K) break;
-        double zz = z[d.seg_param[k - 1]];
-        zseg[k] = d.seg_half[k - 1] ? T(zz * 0.5) : T(zz);
+        if (k <= K) {
+            double zz = z[d.seg_param[k - 1]];
+            zseg[k] = d.seg_half[k - 1] ? T(zz * 0.5) : T(zz);
+        } else {
+            zseg[k] = T(0.0);
+        }
     }
-    for (int a = 0; a < N; ++a) {
-        if (a >= L) break;
-        zph[a] = T(z[d.ph_param[a]]);
-    }
+#pragma unroll
+    for (int a = 0; a < N; ++a) zph[a] = a < L ? T(z[d.ph_param[a]]) : T(1.0);
+    uint32_t span[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) span[a] = a < L ? d.span[a] : 0u;
     // loop matrix Lambda_ab = delta_ab z_gamma_a + sum_{k in span a & span b} z_k
     T Lam[N][N];
+#pragma unroll
     for (int a = 0; a < N; ++a)
-        for (int b = 0; b < N; ++b) Lam[a][b] = T(0.0);
-    for (int a = 0; a < L; ++a) {
-        Lam[a][a] = zph[a];
-        for (int b = 0; b < L; ++b) {
-            uint32_t both = d.span[a] & d.span[b];
-            for (int k = 1; k <= K; ++k)
-                if ((both >> (k - 1)) & 1u) Lam[a][b] += zseg[k];
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            T v = (a == b) ? zph[a] : T(0.0);
+            uint32_t both = span[a] & span[b];
+#pragma unroll
+            for (int k = 1; k <= KM; ++k)
+                if ((both >> (k - 1)) & 1u) v += zseg[k];
+            Lam[a][b] = v;
         }
-    }
-    // LDL^T
-    T Lw[N][N], D[N];
+    // LDL^T (rows a >= L are decoupled identity-like rows with pivot z_ph = 1)
+    T Lw[N][N], D[N], Dinv[N];
     T U = T(1.0);
-    for (int i = 0; i < L; ++i) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
         T di = Lam[i][i];
+#pragma unroll
         for (int j = 0; j < i; ++j) di -= Lw[i][j] * Lw[i][j] * D[j];
         D[i] = di;
-        U *= di;
-        for (int r = i + 1; r < L; ++r) {
+        if (i < L) U *= di;
+        Dinv[i] = T(1.0) / di;
+#pragma unroll
+        for (int r = i + 1; r < N; ++r) {
             T v = Lam[r][i];
+#pragma unroll
             for (int j = 0; j < i; ++j) v -= Lw[r][j] * Lw[i][j] * D[j];
-            Lw[r][i] = v / di;
+            Lw[r][i] = v * Dinv[i];
         }
     }
-    T Dinv[N];
-    for (int i = 0; i < L; ++i) Dinv[i] = T(1.0) / D[i];
     // y_k = L^{-1} s_k
     T y[KM + 1][N];
-    for (int k = 1; k <= K; ++k) {
-        for (int a = 0; a < L; ++a) {
-            T v = ((d.span[a] >> (k - 1)) & 1u) ? T(1.0) : T(0.0);
+#pragma unroll
+    for (int k = 1; k <= KM; ++k)
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            T v = ((span[a] >> (k - 1)) & 1u) ? T(1.0) : T(0.0);
+#pragma unroll
             for (int b = 0; b < a; ++b) v -= Lw[a][b] * y[k][b];
             y[k][a] = v;
         }
-    }
-    // sigma, w = L^{-1} sigma, V = sum w^2/D
+    // sigma, w = L^{-1} sigma, V = sum w^2 / D
     T w[N];
     T V = T(0.0);
-    for (int a = 0; a < L; ++a) {
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
         T sg = T(0.0);
-        for (int k = 1; k <= K; ++k)
-            if ((d.span[a] >> (k - 1)) & 1u) sg += zseg[k];
+#pragma unroll
+        for (int k = 1; k <= KM; ++k)
+            if ((span[a] >> (k - 1)) & 1u) sg += zseg[k];
+#pragma unroll
         for (int b = 0; b < a; ++b) sg -= Lw[a][b] * w[b];
         w[a] = sg;
         V += w[a] * w[a] * Dinv[a];
     }
-    vtot += V;
-    T vars[Dims<N>::NV];
+    vtot += strip(V);
+    U = strip(U);
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        w[a] = strip(w[a]);
+        Dinv[a] = strip(Dinv[a]);
+#pragma unroll
+        for (int k = 1; k <= KM; ++k) y[k][a] = strip(y[k][a]);
+    }
+    vars.begin();
     const int XN = amm_xn(K);
-    for (int k = 1; k <= K; ++k) {
-        for (int k2 = k; k2 <= K; ++k2) {
+#pragma unroll
+    for (int k = 1; k <= KM; ++k) {
+        if (k > K) break;
+#pragma unroll
+        for (int k2 = k; k2 <= KM; ++k2) {
+            if (k2 > K) break;
             T s = T(0.0);
-            for (int a = 0; a < L; ++a) s += y[k][a] * y[k2][a] * Dinv[a];
-            vars[amm_xidx(K, k, k2)] = s;
+#pragma unroll
+            for (int a = 0; a < N; ++a) s += y[k][a] * y[k2][a] * Dinv[a];
+            vars.set(amm_xidx(K, k, k2), s);
         }
         T s = T(0.0);
-        for (int a = 0; a < L; ++a) s += y[k][a] * w[a] * Dinv[a];
-        vars[XN + k - 1] = T(1.0) - s;
+#pragma unroll
+        for (int a = 0; a < N; ++a) s += y[k][a] * w[a] * Dinv[a];
+        vars.set(XN + k - 1, T(1.0) - s);
     }
     if (d.op == OP_A) {
         T wc[N];
-        for (int a = 0; a < L; ++a) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
             T jc = T(0.0);
-            for (int k = 1; k <= K; ++k)
-                if ((d.span[a] >> (k - 1)) & 1u) jc += zseg[k] * T(k <= d.ext_node ? -0.5 : 0.5);
+#pragma unroll
+            for (int k = 1; k <= KM; ++k)
+                if ((span[a] >> (k - 1)) & 1u) jc += zseg[k] * T(k <= d.ext_node ? -0.5 : 0.5);
+#pragma unroll
             for (int b = 0; b < a; ++b) jc -= Lw[a][b] * wc[b];
             wc[a] = jc;
         }
-        for (int k = 1; k <= K; ++k) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) wc[a] = strip(wc[a]);
+#pragma unroll
+        for (int k = 1; k <= KM; ++k) {
+            if (k > K) break;
             T s = T(0.0);
-            for (int a = 0; a < L; ++a) s += y[k][a] * wc[a] * Dinv[a];
-            vars[XN + K + k - 1] = T(k <= d.ext_node ? -0.5 : 0.5) - s;
+#pragma unroll
+            for (int a = 0; a < N; ++a) s += y[k][a] * wc[a] * Dinv[a];
+            vars.set(XN + K + k - 1, T(k <= d.ext_node ? -0.5 : 0.5) - s);
         }
     }
     // prefactor per c: pref (-1/2)^c / U^2 (* z_e for the merged line)
     T base = T(d.pref) / (U * U);
     if (d.has_X) {
-        for (int k = 1; k <= K; ++k)
-            if (d.seg_half[k - 1]) { base = base * (zseg[k] + zseg[k]); break; }
+#pragma unroll
+        for (int k = 1; k <= KM; ++k)
+            if (k <= K && d.seg_half[k - 1]) { base = base * (zseg[k] + zseg[k]); break; }
     }
     // children: on stack at sp - nkids .. sp - 1 (node order)
     const int nk = d.nkids;
     const int kid0 = sp - nk;
     T prodV[N];
     prodV[0] = T(1.0);
+#pragma unroll
     for (int c = 1; c < N; ++c) prodV[c] = T(0.0);
     for (int q = 0; q < nk; ++q) {
         if ((d.kid_is_se >> q) & 1u) continue;
         T tmp[N];
         conv_into<T, N>(prodV, stk[kid0 + q][0], tmp);
+#pragma unroll
         for (int c = 0; c < N; ++c) prodV[c] = tmp[c];
     }
     T res[2][N];
+#pragma unroll
     for (int o = 0; o < 2; ++o)
+#pragma unroll
         for (int c = 0; c < N; ++c) res[o][c] = T(0.0);
     for (int var = 0; var < d.nvariants; ++var) {
         // product of SE children's chosen outputs
         T sev[N];
+#pragma unroll
         for (int c = 0; c < N; ++c) sev[c] = prodV[c];
         int bit = 0;
         for (int q = 0; q < nk; ++q) {
@@ -422,19 +571,23 @@ AMM_HDI void eval_level(const PlanDev &P, const LevelDesc &d, const double *z,
             int ch = (var >> bit) & 1;
             ++bit;
             T tmp[N];
-            conv_into<T, N>(sev, stk[kid0 + q][ch], tmp);
+            if (ch) conv_into<T, N>(sev, stk[kid0 + q][1], tmp);
+            else conv_into<T, N>(sev, stk[kid0 + q][0], tmp);
+#pragma unroll
             for (int c = 0; c < N; ++c) sev[c] = tmp[c];
         }
-        for (int o = 0; o < d.nout; ++o) {
+        for (int o = 0; o < 2; ++o) {
+            if (o >= d.nout) break;
             T own[N];
             T fac = base;
+#pragma unroll
             for (int c = 0; c < N; ++c) {
                 int2 r = P.ranges[d.mono_range + (var * d.nout + o) * (P.n + 1) + c];
                 T acc = T(0.0);
                 for (int m = r.x; m < r.y; ++m) {
                     const Mono &mo = P.monos[m];
-                    T t = mo.nv ? vars[mo.v[0]] : T(1.0);
-                    for (int i = 1; i < mo.nv; ++i) t = t * vars[mo.v[i]];
+                    T t = mo.nv ? vars.get(mo.v[0]) : T(1.0);
+                    for (int i = 1; i < mo.nv; ++i) t = t * vars.get(mo.v[i]);
                     acc = mul_add(T(mo.coef), t, acc);
                 }
                 own[c] = acc * fac;
@@ -447,18 +600,21 @@ AMM_HDI void eval_level(const PlanDev &P, const LevelDesc &d, const double *z,
 #endif
             T tmp[N];
             conv_into<T, N>(own, sev, tmp);
+#pragma unroll
             for (int c = 0; c < N; ++c) res[o][c] += tmp[c];
         }
     }
     sp = kid0;
+#pragma unroll
     for (int o = 0; o < 2; ++o)
+#pragma unroll
         for (int c = 0; c < N; ++c) stk[sp][o][c] = res[o][c];
     ++sp;
 }
 
 // All insertion integrands of one SE graph at z: I[e], and sum |term| absI[e].
-template <typename T, int N>
-AMM_HDI void eval_graph(const PlanDev &P, const double *z, T *I, T *absI) {
+template <typename T, int N, typename Vars>
+AMM_HDI void eval_graph(const PlanDev &P, const double *z, T *I, T *absI, Vars &vars) {
     for (int e = 0; e < P.ninsert; ++e) { I[e] = T(0.0); absI[e] = T(0.0); }
     T stk[Dims<N>::DEPTH][2][N];
     for (int t = 0; t < P.nterms; ++t) {
@@ -467,24 +623,30 @@ AMM_HDI void eval_graph(const PlanDev &P, const double *z, T *I, T *absI) {
         T vtot = T(0.0);
         for (int o = td.op_begin; o < td.op_end; ++o) {
             const LevelDesc &d = P.levels[P.ops[o]];
-            eval_level<T, N>(P, d, z, stk, sp, vtot);
+            eval_level<T, N>(P, d, z, stk, sp, vtot, vars);
         }
         // sum_c vec[c] Gamma(n-c) / V^{n-c}
         T val = T(0.0);
         T vinv = T(1.0) / vtot;
         T vp = vinv;                     // V^-(n-c) built from c = n-1 down
         double gam = 1.0;                // Gamma(n-c) = (n-c-1)!
+#pragma unroll
         for (int c = N - 1; c >= 0; --c) {
-            if (c < P.n) {
-                val = mul_add(stk[0][0][c] * T(gam), vp, val);
-                vp = vp * vinv;
-                gam = gam * (double)(P.n - c);
-            }
+            val = mul_add(stk[0][0][c] * T(gam), vp, val);
+            vp = vp * vinv;
+            gam = gam * (double)(N - c);
         }
         T sv = td.sign > 0 ? val : -val;
         I[td.e] += sv;
         absI[td.e] += absd(val);
     }
+}
+
+// Private-storage convenience overload (host tests, double-double path).
+template <typename T, int N>
+AMM_HDI void eval_graph(const PlanDev &P, const double *z, T *I, T *absI) {
+    VarsPriv<T, Dims<N>::NV> vars;
+    eval_graph<T, N>(P, z, I, absI, vars);
 }
 
 }  // namespace amm

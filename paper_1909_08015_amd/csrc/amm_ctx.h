@@ -1,0 +1,87 @@
+// amm_ctx.h -- library context (internal; shared by the HIP translation units).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "amm_core.h"
+#include "amm_mlp.h"
+
+namespace amm {
+
+int fail(int code, const std::string &msg);
+
+#define HIPCHK(x)                                                                      \
+    do {                                                                               \
+        hipError_t e_ = (x);                                                           \
+        if (e_ != hipSuccess)                                                          \
+            return ::amm::fail(AMM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int BLOCK = 128;
+constexpr int RPC = 64;                       // rounds per chunk
+constexpr int CHUNK = BLOCK * RPC;            // samples per chunk
+constexpr int MAX_CHUNKS_PER_LAUNCH = 4096;
+constexpr double KAPPA = 64.0;                // round-off bound multiplier (reading R11)
+constexpr int MAXNE = 2 * MAXN - 1;
+constexpr int NSTAT_MAX = 3 * MAXNE + 2 * MAXNE + 4;
+
+struct GraphSlot {
+    bool built = false;
+    int n = 0, M = 0, ne = 0, ncls = 0;
+    int cls_of[MAXNE] = {0};
+    int cls_kmm[MAXNE][3];
+    uint32_t uid = 0;
+    PlanHost plan;
+    DensityTables dens;
+    // device copies
+    LevelDesc *d_levels = nullptr;
+    TermDesc *d_terms = nullptr;
+    int32_t *d_ops = nullptr;
+    Mono *d_monos = nullptr;
+    int2 *d_ranges = nullptr;
+    double *d_deg1 = nullptr, *d_deg3 = nullptr, *d_W1 = nullptr, *d_logdeg1 = nullptr;
+    float *d_ptheta = nullptr;                // learned P_theta(j|s) [2^M * M]
+    double *d_pilotW = nullptr;               // pilot W(s, j) [2^M * M]
+    // accumulators (host mirror after read)
+    std::vector<double> acc;                  // NSTAT
+    int nstat() const { return 3 * ne + 2 * ncls + 4; }
+    PlanDev plan_dev() const {
+        PlanDev p;
+        p.levels = d_levels; p.terms = d_terms; p.ops = d_ops; p.monos = d_monos; p.ranges = d_ranges;
+        p.nterms = (int)plan.terms.size(); p.n = n; p.ninsert = ne;
+        return p;
+    }
+    DensityDev dens_dev(bool learned) const {
+        DensityDev D;
+        D.deg1 = d_deg1; D.deg3 = d_deg3; D.W1 = d_W1; D.logdeg1 = d_logdeg1;
+        for (int c = 0; c < 4; ++c) { D.logK[c] = dens.logK[c]; D.logc[c] = dens.logc[c]; D.c[c] = dens.c[c]; }
+        D.ptheta = learned ? d_ptheta : nullptr;
+        D.logc_mix = 0;
+        return D;
+    }
+};
+
+}  // namespace amm
+
+struct amm_ctx {
+    int device = 0;
+    int loops = 0;
+    std::vector<amm::SEGraph> graphs;
+    std::vector<amm::GraphSlot> slots;
+    hipStream_t last_stream = nullptr;
+    double *d_acc = nullptr;            // [graphs * NSTAT_MAX]
+    double *d_part = nullptr;           // chunk partials [MAX_CHUNKS * NSTAT_MAX]
+    uint32_t *d_flag = nullptr;         // flagged offsets [MAX_CHUNKS * CHUNK]
+    int32_t *d_nflag = nullptr;         // per chunk
+    amm::MlpState mlp;
+    // profiling
+    bool prof = false;
+    struct Ev { hipEvent_t a, b, c, d; int64_t samples; };
+    std::vector<Ev> evs;
+    double prof_ms[3] = {0, 0, 0};
+    int64_t prof_launch = 0, prof_samples = 0;
+    ~amm_ctx();
+};
+

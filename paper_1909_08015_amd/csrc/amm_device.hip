@@ -15,95 +15,21 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <type_traits>
 #include <string>
 #include <vector>
 
-#include "amm_core.h"
-#include "amm_mlp.h"
+#include "amm_ctx.h"
 
 using namespace amm;
 
-namespace {
-
+namespace amm {
 thread_local std::string g_err;
-
 int fail(int code, const std::string &msg) {
     g_err = msg;
     return code;
 }
-
-#define HIPCHK(x)                                                                      \
-    do {                                                                               \
-        hipError_t e_ = (x);                                                           \
-        if (e_ != hipSuccess)                                                          \
-            return fail(AMM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_));     \
-    } while (0)
-
-constexpr int BLOCK = 256;
-constexpr int RPC = 64;                       // rounds per chunk
-constexpr int CHUNK = BLOCK * RPC;            // samples per chunk
-constexpr int MAX_CHUNKS_PER_LAUNCH = 4096;
-constexpr double KAPPA = 64.0;                // round-off bound multiplier (reading R11)
-constexpr int MAXNE = 2 * MAXN - 1;
-constexpr int NSTAT_MAX = 3 * MAXNE + 2 * MAXNE + 4;
-
-struct GraphSlot {
-    bool built = false;
-    int n = 0, M = 0, ne = 0, ncls = 0;
-    int cls_of[MAXNE] = {0};
-    int cls_kmm[MAXNE][3];
-    uint32_t uid = 0;
-    PlanHost plan;
-    DensityTables dens;
-    // device copies
-    LevelDesc *d_levels = nullptr;
-    TermDesc *d_terms = nullptr;
-    int32_t *d_ops = nullptr;
-    Mono *d_monos = nullptr;
-    int2 *d_ranges = nullptr;
-    double *d_deg1 = nullptr, *d_deg3 = nullptr, *d_W1 = nullptr, *d_logdeg1 = nullptr;
-    float *d_ptheta = nullptr;                // learned P_theta(j|s) [2^M * M]
-    double *d_pilotW = nullptr;               // pilot W(s, j) [2^M * M]
-    // accumulators (host mirror after read)
-    std::vector<double> acc;                  // NSTAT
-    int nstat() const { return 3 * ne + 2 * ncls + 4; }
-    PlanDev plan_dev() const {
-        PlanDev p;
-        p.levels = d_levels; p.terms = d_terms; p.ops = d_ops; p.monos = d_monos; p.ranges = d_ranges;
-        p.nterms = (int)plan.terms.size(); p.n = n; p.ninsert = ne;
-        return p;
-    }
-    DensityDev dens_dev(bool learned) const {
-        DensityDev D;
-        D.deg1 = d_deg1; D.deg3 = d_deg3; D.W1 = d_W1; D.logdeg1 = d_logdeg1;
-        for (int c = 0; c < 4; ++c) { D.logK[c] = dens.logK[c]; D.logc[c] = dens.logc[c]; D.c[c] = dens.c[c]; }
-        D.ptheta = learned ? d_ptheta : nullptr;
-        D.logc_mix = 0;
-        return D;
-    }
-};
-
-}  // namespace
-
-struct amm_ctx {
-    int device = 0;
-    int loops = 0;
-    std::vector<SEGraph> graphs;
-    std::vector<GraphSlot> slots;
-    hipStream_t last_stream = nullptr;
-    double *d_acc = nullptr;            // [graphs * NSTAT_MAX]
-    double *d_part = nullptr;           // chunk partials [MAX_CHUNKS * NSTAT_MAX]
-    uint32_t *d_flag = nullptr;         // flagged offsets [MAX_CHUNKS * CHUNK]
-    int32_t *d_nflag = nullptr;         // per chunk
-    MlpState mlp;
-    // profiling
-    bool prof = false;
-    struct Ev { hipEvent_t a, b, c, d; int64_t samples; };
-    std::vector<Ev> evs;
-    double prof_ms[3] = {0, 0, 0};
-    int64_t prof_launch = 0, prof_samples = 0;
-    ~amm_ctx();
-};
+}  // namespace amm
 
 amm_ctx::~amm_ctx() {
     hipSetDevice(device);
@@ -126,7 +52,7 @@ __global__ void __launch_bounds__(BLOCK) k_sample(DensityDev D, uint32_t uid, ui
     if (i >= n) return;
     double u[2 * M], zz[M];
     int pp[M];
-    uniforms(seed, uid, c0 + i, 2 * M - 1, u);
+    uniforms(seed, uid, c0 + i, D.ptheta ? 2 * M : 2 * M - 1, u);
     SampleOut o = sample_point<M>(D, u, zz, pp);
     if (z) for (int j = 0; j < M; ++j) z[i * M + j] = zz[j];
     if (path) for (int j = 0; j < M; ++j) path[i * M + j] = pp[j];
@@ -135,18 +61,28 @@ __global__ void __launch_bounds__(BLOCK) k_sample(DensityDev D, uint32_t uid, ui
     if (comp) comp[i] = o.comp;
 }
 
+// T = ea: FP64 value with its round-off bound KAPPA u I.a; T = dd: double-double.
 template <typename T, int N>
-__global__ void __launch_bounds__(BLOCK) k_eval(PlanDev P, const double *z, uint64_t n, double *I, double *absI) {
+__global__ void __launch_bounds__(BLOCK) k_eval(PlanDev P, const double *z, uint64_t n, double *I, double *absI,
+                                                double *bound) {
     constexpr int M = 3 * N - 1, NE = 2 * N - 1;
     uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
+    __shared__ double vlds[Dims<N>::NV * BLOCK];
+    __shared__ float rlds[Dims<N>::NV * BLOCK];
     double zz[M];
     for (int j = 0; j < M; ++j) zz[j] = z[i * M + j];
     T v[NE], a[NE];
-    eval_graph<T, N>(P, zz, v, a);
+    if constexpr (std::is_same<T, ea>::value) {
+        VarsLdsEa vars{vlds + threadIdx.x, rlds + threadIdx.x, BLOCK};
+        eval_graph<T, N>(P, zz, v, a, vars);
+    } else {
+        eval_graph<T, N>(P, zz, v, a);
+    }
     for (int e = 0; e < NE; ++e) {
         if (I) I[i * NE + e] = to_double(v[e]);
         if (absI) absI[i * NE + e] = to_double(a[e]);
+        if (bound) bound[i * NE + e] = KAPPA * 0x1p-53 * mag(v[e]);
     }
 }
 
@@ -199,11 +135,11 @@ __device__ __forceinline__ void add_stats(double (&st)[3 * (2 * N - 1) + 2 * (2 
 
 template <int N>
 __device__ __forceinline__ void eval_sample(const PlanDev &P, const DensityDev &D, const RunArgs &A, uint64_t idx,
-                                            double *y, int &ood, int &flag) {
+                                            double *y, int &ood, int &flag, double *vlds, float *rlds) {
     constexpr int M = 3 * N - 1, NE = 2 * N - 1;
     double u[2 * M], z[M];
     int path[M];
-    uniforms(A.seed, A.uid, idx, 2 * M - 1, u);
+    uniforms(A.seed, A.uid, idx, D.ptheta ? 2 * M : 2 * M - 1, u);
     SampleOut o = sample_point<M>(D, u, z, path);
     ood = o.ood;
     flag = 0;
@@ -211,13 +147,24 @@ __device__ __forceinline__ void eval_sample(const PlanDev &P, const DensityDev &
         for (int e = 0; e < NE; ++e) y[e] = 0.0;
         return;
     }
-    double I[NE], aI[NE];
-    eval_graph<double, N>(P, z, I, aI);
-    for (int e = 0; e < NE; ++e) {
-        double ye = ldexp(I[e] / o.gx, -o.gj);
-        double r = KAPPA * 0x1p-53 * ldexp(aI[e] / o.gx, -o.gj);
-        if (!(r <= A.tau) || !isfinite(ye)) flag = 1;
-        y[e] = ye;
+    if (A.tau == INFINITY) {           // no round-off check requested
+        double I[NE], aI[NE];
+        VarsLdsD vars{vlds + threadIdx.x, BLOCK};
+        eval_graph<double, N>(P, z, I, aI, vars);
+        for (int e = 0; e < NE; ++e) {
+            y[e] = ldexp(I[e] / o.gx, -o.gj);
+            if (!isfinite(y[e])) flag = 1;
+        }
+    } else {
+        ea I[NE], aI[NE];
+        VarsLdsEa vars{vlds + threadIdx.x, rlds + threadIdx.x, BLOCK};
+        eval_graph<ea, N>(P, z, I, aI, vars);
+        for (int e = 0; e < NE; ++e) {
+            double ye = ldexp(I[e].v / o.gx, -o.gj);
+            double r = KAPPA * 0x1p-53 * ldexp(I[e].a / o.gx, -o.gj);
+            if (!(r <= A.tau) || !isfinite(ye)) flag = 1;
+            y[e] = ye;
+        }
     }
     if (flag)
         for (int e = 0; e < NE; ++e) y[e] = 0.0;
@@ -230,6 +177,8 @@ __global__ void __launch_bounds__(BLOCK) k_integrate(PlanDev P, DensityDev D, Ru
     constexpr int NST = 3 * NE + 2 * NE + 4;
     __shared__ double sh[BLOCK];
     __shared__ int shc[BLOCK];
+    __shared__ double vlds[Dims<N>::NV * BLOCK];
+    __shared__ float rlds[Dims<N>::NV * BLOCK];
     const int nst = 3 * NE + 2 * A.ncls + 4;
     for (int ch = blockIdx.x; ch < A.nchunks; ch += gridDim.x) {
         double st[NST];
@@ -242,7 +191,7 @@ __global__ void __launch_bounds__(BLOCK) k_integrate(PlanDev P, DensityDev D, Ru
             double y[NE];
             bool live = idx < A.end;
             if (live) {
-                eval_sample<N>(P, D, A, idx, y, ood, flag);
+                eval_sample<N>(P, D, A, idx, y, ood, flag, vlds, rlds);
                 add_stats<N>(st, y, A);
                 st[nst - 4] += 1.0;
                 st[nst - 3] += flag;
@@ -289,15 +238,17 @@ __global__ void __launch_bounds__(BLOCK) k_dd(PlanDev P, DensityDev D, RunArgs A
             uint64_t idx = base + flags[(size_t)ch * CHUNK + f];
             double u[2 * M], z[M];
             int path[M];
-            uniforms(A.seed, A.uid, idx, 2 * M - 1, u);
+            uniforms(A.seed, A.uid, idx, D.ptheta ? 2 * M : 2 * M - 1, u);
             SampleOut o = sample_point<M>(D, u, z, path);
+            ea Im[NE], aIm[NE];
+            eval_graph<ea, N>(P, z, Im, aIm);
             dd I[NE], aI[NE];
             eval_graph<dd, N>(P, z, I, aI);
             double y[NE];
             int fail = 0;
             for (int e = 0; e < NE; ++e) {
                 double ye = ldexp(to_double(I[e]) / o.gx, -o.gj);
-                double r = KAPPA * 0x1p-104 * ldexp(to_double(aI[e]) / o.gx, -o.gj);
+                double r = KAPPA * 0x1p-104 * ldexp(Im[e].a / o.gx, -o.gj);
                 if (!(r <= fabs(A.tau) || A.tau < 0) || !isfinite(ye)) fail = 1;
                 y[e] = ye;
             }
@@ -343,9 +294,10 @@ int upload(X **dst, const X *src, size_t count) {
 int grid_for(uint64_t n) { return (int)((n + BLOCK - 1) / BLOCK); }
 
 template <int N>
-void launch_eval(const PlanDev &P, const double *z, uint64_t n, double *I, double *a, int prec, hipStream_t s) {
-    if (prec) hipLaunchKernelGGL((k_eval<dd, N>), dim3(grid_for(n)), dim3(BLOCK), 0, s, P, z, n, I, a);
-    else hipLaunchKernelGGL((k_eval<double, N>), dim3(grid_for(n)), dim3(BLOCK), 0, s, P, z, n, I, a);
+void launch_eval(const PlanDev &P, const double *z, uint64_t n, double *I, double *a, double *b, int prec,
+                 hipStream_t s) {
+    if (prec) hipLaunchKernelGGL((k_eval<dd, N>), dim3(grid_for(n)), dim3(BLOCK), 0, s, P, z, n, I, a, b);
+    else hipLaunchKernelGGL((k_eval<ea, N>), dim3(grid_for(n)), dim3(BLOCK), 0, s, P, z, n, I, a, b);
 }
 
 template <int N>
@@ -380,7 +332,7 @@ void prof_collect(amm_ctx *c) {
 // ---------------------------------------------------------------------------
 extern "C" {
 
-const char *amm_last_error(void) { return g_err.c_str(); }
+const char *amm_last_error(void) { return amm::g_err.c_str(); }
 
 int amm_create(amm_ctx **out, int device) {
     if (!out) return fail(AMM_E_ARG, "amm_create: out is NULL");
@@ -500,15 +452,16 @@ int amm_plan_stats(const amm_ctx *c, int g, amm_plan_info *out) {
     return AMM_OK;
 }
 
-int amm_sample(amm_ctx *c, int g, uint64_t seed, uint64_t c0, uint64_t n, double *z, double *gx, int32_t *gj,
-               int32_t *path, int32_t *comp, void *stream) {
+int amm_sample(amm_ctx *c, int g, uint64_t seed, uint64_t c0, uint64_t n, int learned, double *z, double *gx,
+               int32_t *gj, int32_t *path, int32_t *comp, void *stream) {
     if (!c || g < 0 || g >= (int)c->slots.size()) return fail(AMM_E_ARG, "amm_sample: bad graph");
     GraphSlot &s = c->slots[g];
     if (!s.built) return fail(AMM_E_NOTBUILT, "amm_sample: tables not built");
     if (n == 0) return AMM_OK;
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(c->device));
-    DensityDev D = s.dens_dev(false);
+    if (learned && !s.d_ptheta) return fail(AMM_E_ARG, "amm_sample: no sector table for the learned mixture");
+    DensityDev D = s.dens_dev(learned != 0);
     dim3 gr(grid_for(n)), bl(BLOCK);
     switch (s.M) {
         case 2: hipLaunchKernelGGL(k_sample<2>, gr, bl, 0, st, D, s.uid, seed, c0, n, z, gx, gj, path, comp); break;
@@ -522,7 +475,8 @@ int amm_sample(amm_ctx *c, int g, uint64_t seed, uint64_t c0, uint64_t n, double
     return AMM_OK;
 }
 
-int amm_eval(amm_ctx *c, int g, const double *z, uint64_t n, double *I, double *absI, int precision, void *stream) {
+int amm_eval(amm_ctx *c, int g, const double *z, uint64_t n, double *I, double *absI, double *bound, int precision,
+             void *stream) {
     if (!c || g < 0 || g >= (int)c->slots.size()) return fail(AMM_E_ARG, "amm_eval: bad argument");
     GraphSlot &s = c->slots[g];
     if (!s.built) return fail(AMM_E_NOTBUILT, "amm_eval: tables not built");
@@ -532,10 +486,10 @@ int amm_eval(amm_ctx *c, int g, const double *z, uint64_t n, double *I, double *
     HIPCHK(hipSetDevice(c->device));
     PlanDev P = s.plan_dev();
     switch (s.n) {
-        case 1: launch_eval<1>(P, z, n, I, absI, precision, st); break;
-        case 2: launch_eval<2>(P, z, n, I, absI, precision, st); break;
-        case 3: launch_eval<3>(P, z, n, I, absI, precision, st); break;
-        case 4: launch_eval<4>(P, z, n, I, absI, precision, st); break;
+        case 1: launch_eval<1>(P, z, n, I, absI, bound, precision, st); break;
+        case 2: launch_eval<2>(P, z, n, I, absI, bound, precision, st); break;
+        case 3: launch_eval<3>(P, z, n, I, absI, bound, precision, st); break;
+        case 4: launch_eval<4>(P, z, n, I, absI, bound, precision, st); break;
         default: return fail(AMM_E_ARG, "amm_eval: unsupported loop order");
     }
     HIPCHK(hipGetLastError());
@@ -620,6 +574,25 @@ int amm_profile(amm_ctx *c, int enable, double *ms_fp64, double *ms_dd, double *
         c->prof_launch = c->prof_samples = 0;
     }
     c->prof = enable != 0;
+    return AMM_OK;
+}
+
+int amm_accept_thresholds(amm_ctx *c, int gb, int ge, uint64_t n_run, double *tau) {
+    if (!c || !tau || gb < 0 || ge > (int)c->slots.size() || gb >= ge || n_run == 0)
+        return fail(AMM_E_ARG, "amm_accept_thresholds: bad argument");
+    std::vector<double> sig(ge - gb);
+    double s1 = 0.0, s2 = 0.0;
+    for (int g = gb; g < ge; ++g) {
+        amm_estimate est;
+        int rc = amm_read(c, g, -1, -1, -1, -1, &est);
+        if (rc) return rc;
+        if (est.n == 0) return fail(AMM_E_ARG, "amm_accept_thresholds: no pilot samples");
+        double sj = est.sigma * std::sqrt((double)est.n / (double)n_run);
+        sig[g - gb] = sj;
+        s1 += sj;
+        s2 += sj * sj;
+    }
+    for (int g = gb; g < ge; ++g) tau[g - gb] = s1 > 0 ? 0.25 * sig[g - gb] * std::sqrt(s2) / s1 : INFINITY;
     return AMM_OK;
 }
 

@@ -564,7 +564,39 @@ std::string poly_key(const std::vector<Item> &items, int op) {
 // ---------------------------------------------------------------------------
 // Density tables (Sec. III.A readings: Deg1 = max(C_bigZ, C_bigF w(s)))
 // ---------------------------------------------------------------------------
-static double omega_set(const SEGraph &g, uint32_t mask) {
+void set_stats(const SEGraph &g, uint32_t mask, int *loops_out, int *comps_out, int *ng_out, int *ne_out) {
+    int n = g.n, M = 3 * n - 1;
+    std::vector<int> par(2 * n);
+    for (int i = 0; i < 2 * n; ++i) par[i] = i;
+    std::function<int(int)> find = [&](int x) { while (par[x] != x) { par[x] = par[par[x]]; x = par[x]; } return x; };
+    std::vector<bool> touched(2 * n, false);
+    int nl = 0, ng = 0;
+    for (int i = 0; i < M; ++i) {
+        if (!((mask >> i) & 1u)) continue;
+        int u, v;
+        if (i < 2 * n - 1) { u = i; v = i + 1; }
+        else { u = g.chords[i - (2 * n - 1)].first; v = g.chords[i - (2 * n - 1)].second; ++ng; }
+        touched[u] = touched[v] = true;
+        ++nl;
+    }
+    int verts = 0;
+    for (int i = 0; i < 2 * n; ++i) if (touched[i]) ++verts;
+    int comps = verts;
+    for (int i = 0; i < M; ++i) {
+        if (!((mask >> i) & 1u)) continue;
+        int u, v;
+        if (i < 2 * n - 1) { u = i; v = i + 1; }
+        else { u = g.chords[i - (2 * n - 1)].first; v = g.chords[i - (2 * n - 1)].second; }
+        int ru = find(u), rv = find(v);
+        if (ru != rv) { par[ru] = rv; --comps; }
+    }
+    if (loops_out) *loops_out = nl - verts + comps;
+    if (comps_out) *comps_out = comps;
+    if (ng_out) *ng_out = ng;
+    if (ne_out) *ne_out = nl - ng;
+}
+
+double omega_set(const SEGraph &g, uint32_t mask) {
     int n = g.n, M = 3 * n - 1;
     int ne = 0, ng = 0;
     std::vector<int> par(2 * n);
@@ -620,6 +652,7 @@ void build_density(const SEGraph &g, const amm_density_params &p, DensityTables 
         if (m != full) d.W1[m] = F[m] / d.deg1[m];
     }
     d.F1full = F[full];
+    d.F1 = F;
     double logF1 = host_log(F[full]);
     double logM = host_log((double)M);
     double fact = 1.0;

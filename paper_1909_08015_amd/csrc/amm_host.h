@@ -35,7 +35,7 @@ struct SEGraph {
 
 struct DensityTables {
     int M = 0;
-    std::vector<double> deg1, deg3, W1, logdeg1;
+    std::vector<double> deg1, deg3, W1, logdeg1, F1;
     double F1full = 0, logK[4] = {0, 0, 0, 0}, logc[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
 };
 
@@ -57,5 +57,7 @@ std::vector<SEGraph> enumerate_se(int n);
 std::array<int, 3> vertex_class(const SEGraph &g, int e);
 void build_density(const SEGraph &g, const amm_density_params &p, DensityTables &d);
 void build_plan(const SEGraph &g, PlanHost &P);
+double omega_set(const SEGraph &g, uint32_t mask);
+void set_stats(const SEGraph &g, uint32_t mask, int *loops, int *comps, int *ng, int *ne);
 
 }  // namespace amm
