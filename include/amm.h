@@ -139,6 +139,13 @@ int amm_eval(amm_ctx *ctx, int g, const double *z, uint64_t n,
  * recompute of flagged points, accumulate) asynchronously on `stream`. */
 int amm_integrate(amm_ctx *ctx, const amm_run_params *run, void *stream);
 
+/* Options.  AMM_OPT_GENERATED (default 1): evaluate integrands with the
+ * straight-line code generated at build time for the graph when it exists
+ * (1-3 loops), else (0, or no generated code) with the table interpreter.
+ * Both compute the same levels and polynomials; results agree to rounding. */
+#define AMM_OPT_GENERATED 1
+int amm_set_option(amm_ctx *ctx, int option, int value);
+
 /* Round-off acceptance thresholds of eq. (interval_accept), Sec. IV.A:
  * tau_j = (1/4) sigma_j sqrt(sum_l sigma_l^2) / sum_l sigma_l over the graphs
  * [graph_begin, graph_end), where sigma_j is the current accumulators'

