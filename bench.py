@@ -67,7 +67,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) != 1:
         print('bench.py: this build runs on one GPU only; multi-GPU runs are not part of it '
-              '(samples shard by counter range; see DESIGN.md)', file=sys.stderr)
+              '(samples shard by Philox counter range across GPUs)', file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -114,7 +114,7 @@ def main():
         "ms_per_step": dt / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "C2 (configs[1]): all 10 three-loop no-lepton-loop SE graphs, 8 Feynman "
+        "config": {"workload": "3-loop set: all 10 three-loop no-lepton-loop SE graphs, 8 Feynman "
                                "parameters, plain combinatorial density (Calc 2), FP64, Philox seed 0; "
                                f"one step = {B} sample counters per graph",
                    "graphs": G, "loops": 3, "batch_per_graph": B, "counters_done": counter},

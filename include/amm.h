@@ -170,17 +170,26 @@ int amm_read(amm_ctx *ctx, int g, int e, int cls_k, int cls_m, int cls_mp,
 int amm_profile(amm_ctx *ctx, int enable, double *ms_fp64, double *ms_dd, double *ms_reduce,
                 int64_t *n_launches, int64_t *n_samples);
 
-/* ----- learned sector sampler (spec extension, not in the paper) -----
+/* ----- learned sector sampler (an extension, not in the paper) -----
  * A 3-layer FP32 MLP maps features of (graph, s, j) to a logit correction of
  * the plain sector probabilities; q = (q_theta + g)/2 stays exactly
  * computable so f/q remains unbiased. */
 
-/* Record pilot statistics: for `n_per_graph` samples of graphs
- * [graph_begin, graph_end) drawn from the plain density with `seed`,
- * accumulate W(s, j) = sum |f|/g over samples whose sector path takes line j
- * from set s. */
+/* Record pilot statistics for graphs [graph_begin, graph_end): samples
+ * [0, n_per_graph) of `seed` drawn from the plain density.  Per sample
+ * w = sqrt(sum_e y_e^2), y_e = I_e / g (FP64, or double-double where the FP64
+ * round-off bound exceeds 1% of w; out-of-double or non-finite points give 0).
+ * With wref = mean of w over the first min(n_per_graph, 2^23) samples, the
+ * integer q = floor(min(w / wref, 256) * 2^24) is added to W(s, j) for every
+ * step (set s, chosen line j) of the sample's sector path; integer sums make
+ * W independent of the order of the additions.  Synchronises the stream.
+ * Errors: AMM_E_ARG (range, n = 0), AMM_E_NOTBUILT, AMM_E_HIP. */
 int amm_pilot(amm_ctx *ctx, uint64_t seed, uint64_t n_per_graph,
               int graph_begin, int graph_end, void *stream);
+/* Copy graph g's pilot table W [2^M x M] (row s = bitmask of the remaining
+ * lines, column j = chosen line; exact integers as doubles) to host memory of
+ * at least cap doubles.  Errors: AMM_E_ARG, AMM_E_NOTBUILT (no pilot yet). */
+int amm_pilot_table(const amm_ctx *ctx, int g, double *host, size_t cap);
 /* Train the MLP on the pilot table for `epochs` full-batch Adam steps with
  * learning rate lr, then tabulate P_theta(j | s) for every built graph. */
 int amm_mlp_train(amm_ctx *ctx, int epochs, float lr, uint64_t init_seed, void *stream);

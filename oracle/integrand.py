@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE (see oracle/graphs.py).
 The paper (Sec. II) defines the operators A, U, L and the forest sum R^new and
 says the operators act on subgraph amplitudes in Feynman-parametric space via
 Schwinger parameters; it does not print the parametric integrand.  This module
-writes that integrand out from first principles (reading R3/R4 in the design doc):
+writes that integrand out from first principles (readings R3/R4):
 
 Level.  Each forest element G_i with its maximal sub-elements contracted is a
 level with L_i loops and N_i lines.  Its Schwinger-parametric amplitude, after

@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE (see oracle/graphs.py).
 
-This part is not in the paper; it follows the specification written for this
-project (reading R15):
+This part is not in the paper; it follows this project's specification of
+the learned sampler:
 
 * rows: every (s, j) with j in s, |s| >= 2, of an SE graph's M lines, ordered
   by s ascending then j ascending; a group = the rows of one s;
@@ -168,3 +168,50 @@ def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** t)
     vh = v / (1 - b2 ** t)
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def pilot_weights(n, gi, seed, count, chunk=20000):
+    """Per-sample pilot weights w_i = sqrt(sum_e y_e^2), y_e = I_e / g, for the
+    samples [0, count) of `seed` drawn from the plain density; out-of-double or
+    non-finite samples get 0.  Returns (w, paths)."""
+    from .estimate import evaluate_points, DBL_MIN
+    ws, paths = [], []
+    dens = None
+    for c0 in range(0, count, chunk):
+        cnt = min(chunk, count - c0)
+        out, dens = S.sample_graph(n, gi, seed, c0, cnt, dens)
+        vals, _ = evaluate_points(n, gi, out['z'])
+        with np.errstate(all='ignore'):
+            y = np.ldexp(vals / out['gx'][:, None], -out['gj'][:, None])
+            w = np.sqrt((y * y).sum(1))
+        w[(out['z'].min(1) < DBL_MIN) | ~np.isfinite(w)] = 0.0
+        ws.append(w)
+        paths.append(out['path'])
+    return np.concatenate(ws), np.concatenate(paths)
+
+
+def pilot_table(n, gi, seed, count, w=None, paths=None):
+    """Pilot table of the learned sampler: W(s, j) = sum of q_i over the samples
+    whose sector path takes line j from set s, with the integer weights
+    q_i = floor(min(w_i / wref, 256) * 2^24) and wref the mean of w over the
+    first min(count, 2^23) samples (integers: the table does not depend on the
+    order of the additions).  Returns W as float64 [2^M, M]."""
+    if w is None:
+        w, paths = pilot_weights(n, gi, seed, count)
+    M = 3 * n - 1
+    m0 = min(count, 1 << 23)
+    wref = float(np.mean(w[:m0])) if m0 else 0.0
+    W = np.zeros((1 << M, M), dtype=np.int64)
+    if not wref > 0.0:
+        return W.astype(np.float64)
+    q = np.floor(np.minimum(w / wref, 256.0) * 16777216.0).astype(np.int64)
+    full = (1 << M) - 1
+    for i in range(len(w)):
+        if q[i] == 0:
+            continue
+        s = full
+        for l in range(M - 1):
+            j = int(paths[i][l])
+            W[s, j] += q[i]
+            s &= ~(1 << j)
+    return W.astype(np.float64)

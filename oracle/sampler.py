@@ -11,7 +11,7 @@ C2 = 0.03, C3 = 0.01, C4 = 0.06, D = 0.75, C1 = 1 - C2 - C3 - C4 (Sec. V);
 g stored as x 2^j with 0.5 <= x < 1 and a 32-bit j (Sec. IV.A).
 
 The sampling algorithm, g2..g4 and the Deg(s) algorithm are in references the
-paper cites but does not reproduce.  Readings used here (DESIGN.md, R6-R8):
+paper cites but does not reproduce.  Readings used here (R6-R8):
 
   * sector coordinates t_l = z_{jl}/z_{jl-1} in (0,1) give
     delta(1-sum z) dz / prod z = prod_{l>=2} dt_l / t_l, so the g1 mass of a

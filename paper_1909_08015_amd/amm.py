@@ -66,6 +66,7 @@ SYMBOLS = {
     'amm_profile': (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                               C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     'amm_pilot': (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64, C.c_int, C.c_int, C.c_void_p]),
+    'amm_pilot_table': (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_size_t]),
     'amm_mlp_train': (C.c_int, [C.c_void_p, C.c_int, C.c_float, C.c_uint64, C.c_void_p]),
     'amm_mlp_params': (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     'amm_mlp_set_params': (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
@@ -219,6 +220,14 @@ class Context:
     def pilot(self, seed, n_per_graph, graph_begin=0, graph_end=None, stream=None):
         graph_end = self.n_se if graph_end is None else graph_end
         _check(lib().amm_pilot(self.h, seed, n_per_graph, graph_begin, graph_end, _stream(stream)), 'amm_pilot')
+
+    def pilot_table(self, g):
+        """Graph g's pilot table W [2^M, M] (float64 holding exact integers)."""
+        import numpy as np
+        M = self.M
+        W = np.empty((1 << M, M), dtype=np.float64)
+        _check(lib().amm_pilot_table(self.h, g, W.ctypes.data_as(C.c_void_p), W.size), 'amm_pilot_table')
+        return W
 
     def mlp_train(self, epochs, lr=1e-2, init_seed=0, stream=None):
         _check(lib().amm_mlp_train(self.h, epochs, lr, init_seed, _stream(stream)), 'amm_mlp_train')

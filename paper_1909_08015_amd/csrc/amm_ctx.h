@@ -20,9 +20,11 @@ int fail(int code, const std::string &msg);
     } while (0)
 
 constexpr int BLOCK = 128;
-constexpr int RPC = 64;                       // rounds per chunk
-constexpr int CHUNK = BLOCK * RPC;            // samples per chunk
-constexpr int MAX_CHUNKS_PER_LAUNCH = 4096;
+constexpr int RPC = 8;                        // rounds per chunk
+constexpr int CHUNK = BLOCK * RPC;            // samples per chunk (the unit of the fixed-order sums)
+constexpr int MAX_CHUNKS_PER_LAUNCH = 8192;   // 8.4M samples per launch
+constexpr int DD_BLOCK = 64;                  // one wave per block in the double-double recompute
+constexpr uint32_t FLAG_DDFAIL = 0x80000000u; // flag word: the DD bound cannot pass either
 constexpr double KAPPA = 64.0;                // round-off bound multiplier (reading R11)
 constexpr int MAXNE = 2 * MAXN - 1;
 constexpr int NSTAT_MAX = 3 * MAXNE + 2 * MAXNE + 4;
@@ -75,6 +77,9 @@ struct amm_ctx {
     double *d_part = nullptr;           // chunk partials [MAX_CHUNKS * NSTAT_MAX]
     uint32_t *d_flag = nullptr;         // flagged offsets [MAX_CHUNKS * CHUNK]
     int32_t *d_nflag = nullptr;         // per chunk
+    int32_t *d_foff = nullptr;          // exclusive scan of d_nflag [MAX_CHUNKS + 1]
+    double *d_ydd = nullptr;            // DD results of flagged points, [ne][MAX_CHUNKS * CHUNK]
+    int ydd_ne = 0;
     amm::MlpState mlp;
     bool use_gen = true;                // generated integrand code when built
     // profiling

@@ -40,7 +40,7 @@ amm_ctx::~amm_ctx() {
         hipFree(s.d_deg1); hipFree(s.d_deg3); hipFree(s.d_W1); hipFree(s.d_logdeg1);
         hipFree(s.d_ptheta); hipFree(s.d_pilotW);
     }
-    hipFree(d_acc); hipFree(d_part); hipFree(d_flag); hipFree(d_nflag);
+    hipFree(d_acc); hipFree(d_part); hipFree(d_flag); hipFree(d_nflag); hipFree(d_foff); hipFree(d_ydd);
     mlp_free(mlp);
 }
 
@@ -63,12 +63,20 @@ __global__ void __launch_bounds__(BLOCK) k_sample(DensityDev D, uint32_t uid, ui
     if (comp) comp[i] = o.comp;
 }
 
-__global__ void k_reduce(const double *part, int nchunks, int nst, double *acc) {
-    int s = threadIdx.x;
-    if (s >= nst) return;
+// acc[s] += sum over chunks of part[chunk][s]: block s, thread t sums chunks
+// t, t+256, ... in order, then a fixed tree over the threads.
+__global__ void __launch_bounds__(256) k_reduce(const double *part, int nchunks, double *acc) {
+    __shared__ double sh[256];
+    const int s = blockIdx.x, t = threadIdx.x;
     double v = 0.0;
-    for (int c = 0; c < nchunks; ++c) v += part[(size_t)c * NSTAT_MAX + s];
-    acc[s] += v;
+    for (int c = t; c < nchunks; c += 256) v += part[(size_t)c * NSTAT_MAX + s];
+    sh[t] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    if (t == 0) acc[s] += sh[0];
 }
 
 __global__ void k_zero(double *p, int n) {
@@ -106,6 +114,8 @@ void launch_eval(const GraphSlot &gs, int g, const double *z, uint64_t n, double
     launch_eval_ev<N, InterpEval, ea>(EV, z, n, I, a, b, s);
 }
 
+constexpr int DD_GRID = 4096;                 // blocks of the per-point DD recompute (grid-stride)
+
 template <int N>
 void launch_run(const GraphSlot &gs, int g, const DensityDev &D, const RunArgs &A, int grid, amm_ctx *c, hipStream_t s,
                 amm_ctx::Ev *ev, bool use_gen) {
@@ -117,7 +127,8 @@ void launch_run(const GraphSlot &gs, int g, const DensityDev &D, const RunArgs &
     else
         launch_fp64_ev<N>(EV, D, A, grid, c->d_part, c->d_flag, c->d_nflag, s);
     if (ev) hipEventRecord(ev->b, s);
-    launch_dd_ev<N>(EV, D, A, grid, c->d_part, c->d_flag, c->d_nflag, s);
+    launch_dd<N>(gs.plan_dev(), D, A, DD_GRID, std::min(A.nchunks, grid), c->d_part, c->d_flag, c->d_nflag, c->d_foff,
+                 c->d_ydd, (size_t)MAX_CHUNKS_PER_LAUNCH * CHUNK, s);
     if (ev) hipEventRecord(ev->c, s);
 }
 
@@ -156,6 +167,7 @@ int amm_create(amm_ctx **out, int device) {
     HIPCHK(hipMalloc((void **)&c->d_part, (size_t)MAX_CHUNKS_PER_LAUNCH * NSTAT_MAX * sizeof(double)));
     HIPCHK(hipMalloc((void **)&c->d_flag, (size_t)MAX_CHUNKS_PER_LAUNCH * CHUNK * sizeof(uint32_t)));
     HIPCHK(hipMalloc((void **)&c->d_nflag, (size_t)MAX_CHUNKS_PER_LAUNCH * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void **)&c->d_foff, (size_t)(MAX_CHUNKS_PER_LAUNCH + 1) * sizeof(int32_t)));
     *out = c.release();
     return AMM_OK;
 }
@@ -316,6 +328,14 @@ int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
     HIPCHK(hipSetDevice(c->device));
     int dev_cus = 256;
     hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    const int ne_ctx = 2 * c->loops - 1;
+    if (c->ydd_ne < ne_ctx) {                 // DD results of up to one launch of samples
+        HIPCHK(hipFree(c->d_ydd));
+        c->d_ydd = nullptr;
+        c->ydd_ne = 0;
+        HIPCHK(hipMalloc((void **)&c->d_ydd, (size_t)ne_ctx * MAX_CHUNKS_PER_LAUNCH * CHUNK * sizeof(double)));
+        c->ydd_ne = ne_ctx;
+    }
     for (int g = r->graph_begin; g < r->graph_end; ++g) {
         GraphSlot &s = c->slots[g];
         if (!s.built) return fail(AMM_E_NOTBUILT, "amm_integrate: tables not built");
@@ -357,7 +377,7 @@ int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
                 case 4: launch_run<4>(s, g, D, A, grid, c, st, evp, c->use_gen); break;
                 default: return fail(AMM_E_ARG, "amm_integrate: unsupported loop order");
             }
-            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, st, c->d_part, nch, s.nstat(),
+            hipLaunchKernelGGL(k_reduce, dim3(s.nstat()), dim3(256), 0, st, c->d_part, nch,
                                c->d_acc + (size_t)g * NSTAT_MAX);
             if (evp) {
                 HIPCHK(hipEventRecord(ev.d, st));

@@ -4,7 +4,9 @@
 //   k_integrate  sample + evaluate + round-off check (eq. interval_accept) +
 //                per-chunk deterministic partial sums; flagged samples are
 //                compacted per chunk in sample order
-//   k_dd         double-double recompute of the flagged samples of a chunk
+//   k_flag_scan  offsets of the flagged samples of a launch
+//   k_dd_points  double-double recompute, one flagged sample per thread
+//   k_dd_reduce  per-chunk sums of the recomputed samples, in flag order
 #pragma once
 #include <type_traits>
 
@@ -31,18 +33,6 @@ struct GenEval {
         G::template eval<T>(z, I, absI);
     }
 };
-
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    double r = sh[0];
-    __syncthreads();
-    return r;
-}
 
 struct RunArgs {
     uint64_t seed, begin, end;      // sample index range [begin, end)
@@ -107,9 +97,13 @@ __device__ __forceinline__ void add_stats(double (&st)[3 * (2 * N - 1) + 2 * (2 
     }
 }
 
+// One sample: point, density, FP64 integrands with their round-off bound and
+// the acceptance test of eq. (interval_accept).  flag: the FP64 value is not
+// accepted (its y is replaced by the recompute); ddbad: the double-double
+// bound (KAPPA 2^-104 a / g) cannot pass either, so the recompute is skipped.
 template <int N, class Ev>
 __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, const RunArgs &A, uint64_t idx,
-                                            double *y, int &ood, int &flag, double *vlds, float *rlds) {
+                                            double *y, int &ood, int &flag, int &ddbad, double *vlds, float *rlds) {
     constexpr int M = 3 * N - 1, NE = 2 * N - 1;
     double u[2 * M], z[M];
     int path[M];
@@ -117,6 +111,7 @@ __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, c
     SampleOut o = sample_point<M>(D, u, z, path);
     ood = o.ood;
     flag = 0;
+    ddbad = 0;
     if (o.ood) {
         for (int e = 0; e < NE; ++e) y[e] = 0.0;
         return;
@@ -144,8 +139,9 @@ __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, c
         }
         for (int e = 0; e < NE; ++e) {
             double ye = ldexp(I[e].v / o.gx, -o.gj);
-            double r = KAPPA * 0x1p-53 * ldexp(I[e].a / o.gx, -o.gj);
-            if (!(r <= A.tau) || !isfinite(ye)) flag = 1;
+            double r = ldexp(I[e].a / o.gx, -o.gj);
+            if (!(KAPPA * 0x1p-53 * r <= A.tau) || !isfinite(ye)) flag = 1;
+            if (A.tau >= 0.0 && !(KAPPA * 0x1p-104 * r <= A.tau)) ddbad = 1;
             y[e] = ye;
         }
     }
@@ -153,16 +149,45 @@ __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, c
         for (int e = 0; e < NE; ++e) y[e] = 0.0;
 }
 
+// Sum over one wavefront (fixed butterfly order; lane 0's value is used).
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Block-wide sums of the statistics: one butterfly per wave, then the waves in
+// order.  Every thread must call it; thread s < nst writes statistic s.
+template <int NST, int NB>
+__device__ __forceinline__ void block_stats(const double (&st)[NST], int nst, double (*shs)[NST], double *out,
+                                            bool add) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int s = 0; s < NST; ++s) {
+        if (s >= nst) break;
+        double v = wave_sum(st[s]);
+        if (lane == 0) shs[wv][s] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nst) {
+        double v = shs[0][threadIdx.x];
+        for (int w = 1; w < NB / 64; ++w) v += shs[w][threadIdx.x];
+        if (add) out[threadIdx.x] += v;
+        else out[threadIdx.x] = v;
+    }
+    __syncthreads();
+}
+
 template <int N, class Ev>
 __global__ void __launch_bounds__(BLOCK) k_integrate(Ev EV, DensityDev D, RunArgs A, double *part, uint32_t *flags,
                                                      int32_t *nflag) {
     constexpr int NE = 2 * N - 1;
     constexpr int NST = 3 * NE + 2 * NE + 4;
-    __shared__ double sh[BLOCK];
-    __shared__ int shc[BLOCK];
+    constexpr int NW = BLOCK / 64;
+    __shared__ double shs[NW][NST];
+    __shared__ int shw[NW];
     __shared__ double vlds[(Ev::kLds ? Dims<N>::NV : 1) * BLOCK];
     __shared__ float rlds[(Ev::kLds ? Dims<N>::NV : 1) * BLOCK];
     const int nst = 3 * NE + 2 * A.ncls + 4;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int ch = blockIdx.x; ch < A.nchunks; ch += gridDim.x) {
         double st[NST];
         for (int s = 0; s < NST; ++s) st[s] = 0.0;
@@ -170,86 +195,138 @@ __global__ void __launch_bounds__(BLOCK) k_integrate(Ev EV, DensityDev D, RunArg
         int fcount = 0;
         for (int r = 0; r < RPC; ++r) {
             uint64_t idx = base + (uint64_t)r * BLOCK + threadIdx.x;
-            int flag = 0, ood = 0;
+            int flag = 0, ood = 0, ddbad = 0;
             double y[NE];
             bool live = idx < A.end;
             if (live) {
-                eval_sample<N>(EV, D, A, idx, y, ood, flag, vlds, rlds);
+                eval_sample<N>(EV, D, A, idx, y, ood, flag, ddbad, vlds, rlds);
                 add_stats<N>(st, y, A);
                 st[nst - 4] += 1.0;
                 st[nst - 3] += flag;
                 st[nst - 1] += ood;
             }
-            // compact flagged offsets of this round in thread order
-            shc[threadIdx.x] = (live && flag) ? 1 : 0;
+            // compact the flagged offsets of this round in thread order
+            const bool f = live && flag;
+            const uint64_t m = __ballot(f);
+            if (lane == 0) shw[wv] = __popcll(m);
             __syncthreads();
-            int pos = 0;
-            for (int t = 0; t < (int)threadIdx.x; ++t) pos += shc[t];
-            int tot = 0;
-            if (threadIdx.x == 0)
-                for (int t = 0; t < BLOCK; ++t) tot += shc[t];
-            if (live && flag) flags[(size_t)ch * CHUNK + fcount + pos] = (uint32_t)(r * BLOCK + threadIdx.x);
-            __syncthreads();
-            if (threadIdx.x == 0) shc[0] = tot;
-            __syncthreads();
-            fcount += shc[0];
+            int pos = fcount + __popcll(m & ((1ull << lane) - 1ull));
+            for (int w = 0; w < wv; ++w) pos += shw[w];
+            if (f) flags[(size_t)ch * CHUNK + pos] = (uint32_t)(r * BLOCK + threadIdx.x) | (ddbad ? FLAG_DDFAIL : 0u);
+            for (int w = 0; w < NW; ++w) fcount += shw[w];
             __syncthreads();
         }
-        for (int s = 0; s < nst; ++s) {
-            double v = block_sum(st[s], sh);
-            if (threadIdx.x == 0) part[(size_t)ch * NSTAT_MAX + s] = v;
-        }
+        block_stats<NST, BLOCK>(st, nst, shs, part + (size_t)ch * NSTAT_MAX, false);
         if (threadIdx.x == 0) nflag[ch] = fcount;
-        __syncthreads();
     }
 }
 
-template <int N, class Ev>
-__global__ void __launch_bounds__(BLOCK) k_dd(Ev EV, DensityDev D, RunArgs A, double *part, const uint32_t *flags,
-                                              const int32_t *nflag) {
+// Exclusive scan of the per-chunk flag counts (one block of 1024 threads;
+// nchunks <= MAX_CHUNKS_PER_LAUNCH): off[0..nchunks], off[nchunks] = total.
+static __global__ void __launch_bounds__(1024) k_flag_scan(const int32_t *nflag, int nchunks, int32_t *off) {
+    constexpr int T = 1024, PER = (MAX_CHUNKS_PER_LAUNCH + T - 1) / T;
+    __shared__ int32_t sh[T];
+    const int t = threadIdx.x;
+    int32_t loc[PER], s = 0;
+    for (int q = 0; q < PER; ++q) {
+        int c = t * PER + q;
+        loc[q] = c < nchunks ? nflag[c] : 0;
+        s += loc[q];
+    }
+    sh[t] = s;
+    __syncthreads();
+    for (int d = 1; d < T; d <<= 1) {          // inclusive Hillis-Steele scan
+        int32_t v = t >= d ? sh[t - d] : 0;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    int32_t run = t ? sh[t - 1] : 0;
+    for (int q = 0; q < PER; ++q) {
+        int c = t * PER + q;
+        if (c < nchunks) off[c] = run;
+        run += loc[q];
+    }
+    if (t == T - 1) off[nchunks] = sh[T - 1];
+}
+
+// Double-double variables in LDS columns (hi and lo parts).
+struct VarsLdsDd {
+    double *hi, *lo;
+    int stride;
+    AMM_HDI void begin() {}
+    AMM_HDI void set(int i, const dd &x) { hi[i * stride] = x.hi; lo[i * stride] = x.lo; }
+    AMM_HDI dd get(int i) const { return dd(hi[i * stride], lo[i * stride]); }
+};
+
+// Double-double recompute, one flagged sample per thread over the whole
+// launch: y_e of flagged point f goes to ydd[e * cap + f]; a point that fails
+// (bound, or a non-finite value) gets NaN in ydd[f].
+template <int N>
+__global__ void __launch_bounds__(DD_BLOCK) k_dd_points(PlanDev P, DensityDev D, RunArgs A, const uint32_t *flags,
+                                                        const int32_t *off, double *ydd, size_t cap) {
     constexpr int M = 3 * N - 1, NE = 2 * N - 1;
-    constexpr int NST = 3 * NE + 2 * NE + 4;
-    __shared__ double sh[BLOCK];
-    const int nst = 3 * NE + 2 * A.ncls + 4;
-    for (int ch = blockIdx.x; ch < A.nchunks; ch += gridDim.x) {
-        int nf = nflag[ch];
-        if (nf == 0) continue;
-        double st[NST];
-        for (int s = 0; s < NST; ++s) st[s] = 0.0;
-        uint64_t base = A.begin + (uint64_t)(A.chunk0 + ch) * CHUNK;
-        for (int f = threadIdx.x; f < nf; f += BLOCK) {
-            uint64_t idx = base + flags[(size_t)ch * CHUNK + f];
+    __shared__ double vh[Dims<N>::NV * DD_BLOCK], vl[Dims<N>::NV * DD_BLOCK];
+    const int nch = A.nchunks;
+    const int32_t total = off[nch];
+    for (int32_t f = blockIdx.x * DD_BLOCK + threadIdx.x; f < total; f += gridDim.x * DD_BLOCK) {
+        int lo = 0, hi = nch;                 // largest chunk with off[chunk] <= f
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (off[mid] <= f) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t w = flags[(size_t)lo * CHUNK + (f - off[lo])];
+        bool fail = (w & FLAG_DDFAIL) != 0u;
+        double y[NE];
+        if (!fail) {
+            uint64_t idx = A.begin + (uint64_t)(A.chunk0 + lo) * CHUNK + (w & ~FLAG_DDFAIL);
             double u[2 * M], z[M];
             int path[M];
             uniforms(A.seed, A.uid, idx, D.ptheta ? 2 * M : 2 * M - 1, u);
             SampleOut o = sample_point<M>(D, u, z, path);
-            ea Im[NE], aIm[NE];
-            VarsPriv<ea, Ev::kLds ? Dims<N>::NV : 1> vm;
-            EV.template eval<ea, N>(z, Im, aIm, vm);
             dd I[NE], aI[NE];
-            VarsPriv<dd, Ev::kLds ? Dims<N>::NV : 1> vd;
-            EV.template eval<dd, N>(z, I, aI, vd);
-            double y[NE];
-            int fail = 0;
+            VarsLdsDd vars{vh + threadIdx.x, vl + threadIdx.x, DD_BLOCK};
+            eval_graph<dd, N>(P, z, I, aI, vars);
             for (int e = 0; e < NE; ++e) {
-                double ye = ldexp(to_double(I[e]) / o.gx, -o.gj);
-                double r = KAPPA * 0x1p-104 * ldexp(Im[e].a / o.gx, -o.gj);
-                if (!(r <= fabs(A.tau) || A.tau < 0) || !isfinite(ye)) fail = 1;
-                y[e] = ye;
+                y[e] = ldexp(to_double(I[e]) / o.gx, -o.gj);
+                if (!isfinite(y[e])) fail = true;
             }
-            if (fail) {
-                for (int e = 0; e < NE; ++e) y[e] = 0.0;
-                st[nst - 2] += 1.0;
-            }
-            add_stats<N>(st, y, A);
         }
-        for (int s = 0; s < nst; ++s) {
-            double v = block_sum(st[s], sh);
-            if (threadIdx.x == 0) part[(size_t)ch * NSTAT_MAX + s] += v;
+        if (fail) {
+            ydd[f] = NAN;
+        } else {
+            for (int e = 0; e < NE; ++e) ydd[(size_t)e * cap + f] = y[e];
         }
     }
 }
 
+// Adds the recomputed samples of each chunk to its partial sums, in flag order.
+template <int N>
+__global__ void __launch_bounds__(BLOCK) k_dd_reduce(RunArgs A, const int32_t *off, const double *ydd, size_t cap,
+                                                     double *part) {
+    constexpr int NE = 2 * N - 1;
+    constexpr int NST = 3 * NE + 2 * NE + 4;
+    __shared__ double shs[BLOCK / 64][NST];
+    const int nst = 3 * NE + 2 * A.ncls + 4;
+    for (int ch = blockIdx.x; ch < A.nchunks; ch += gridDim.x) {
+        const int32_t a = off[ch], b = off[ch + 1];
+        if (a == b) continue;                 // uniform over the block
+        double st[NST];
+        for (int s = 0; s < NST; ++s) st[s] = 0.0;
+        for (int32_t f = a + threadIdx.x; f < b; f += BLOCK) {
+            double y[NE];
+            if (isnan(ydd[f])) {
+                for (int e = 0; e < NE; ++e) y[e] = 0.0;
+                st[nst - 2] += 1.0;
+            } else {
+                for (int e = 0; e < NE; ++e) y[e] = ydd[(size_t)e * cap + f];
+            }
+            add_stats<N>(st, y, A);
+        }
+        block_stats<NST, BLOCK>(st, nst, shs, part + (size_t)ch * NSTAT_MAX, true);
+    }
+}
 
 // Launch the FP64 pass of one chunk batch.
 template <int N, class Ev>
@@ -258,11 +335,14 @@ void launch_fp64_ev(const Ev &EV, const DensityDev &D, const RunArgs &A, int gri
     hipLaunchKernelGGL((k_integrate<N, Ev>), dim3(grid), dim3(BLOCK), 0, s, EV, D, A, part, flag, nflag);
 }
 
-// Launch the double-double recompute of the flagged samples of a chunk batch.
-template <int N, class Ev>
-void launch_dd_ev(const Ev &EV, const DensityDev &D, const RunArgs &A, int grid, double *part, uint32_t *flag,
-                  int32_t *nflag, hipStream_t s) {
-    hipLaunchKernelGGL((k_dd<N, Ev>), dim3(grid), dim3(BLOCK), 0, s, EV, D, A, part, flag, nflag);
+// Launch the double-double recompute of the flagged samples of a chunk batch
+// (scan, per-point recompute, per-chunk sums).
+template <int N>
+void launch_dd(const PlanDev &P, const DensityDev &D, const RunArgs &A, int grid_pts, int grid_red, double *part,
+               const uint32_t *flag, const int32_t *nflag, int32_t *off, double *ydd, size_t cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, s, nflag, A.nchunks, off);
+    hipLaunchKernelGGL((k_dd_points<N>), dim3(grid_pts), dim3(DD_BLOCK), 0, s, P, D, A, flag, off, ydd, cap);
+    hipLaunchKernelGGL((k_dd_reduce<N>), dim3(grid_red), dim3(BLOCK), 0, s, A, off, ydd, cap, part);
 }
 
 template <int N, class Ev, typename T>

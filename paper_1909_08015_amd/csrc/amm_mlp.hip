@@ -1,9 +1,10 @@
 // amm_mlp.hip -- learned sector sampler: pilot statistics, MLP training and
-// tabulation (spec extension; the paper's density is the fallback).
+// tabulation (an extension beyond the paper; the paper's density is the fallback).
 //
 // Pilot: samples from the plain density g; each sample's weight
-// w = sqrt(sum_e y_e^2) (y = I/g per insertion) is added to W(s, j) for every
-// (set s, chosen line j) on its sector path.  Training minimises
+// w = sqrt(sum_e y_e^2) (y = I/g per insertion), quantised to an integer
+// relative to the mean weight, is added to W(s, j) for every (set s, chosen
+// line j) on its sector path (integer sums: the table is reproducible).  Training minimises
 // -sum w_row log P_theta(j|s) with P_theta = softmax_j(log P0(j|s) + d(s,j)),
 // d the MLP output; the gradient is reduced per fixed tile in a fixed order.
 #include <hip/hip_runtime.h>
@@ -22,35 +23,96 @@ constexpr int MB = 64;          // rows per backward tile
 constexpr int BW_BLOCKS = 512;  // backward grid (fixed: deterministic sums)
 
 // ---------------------------------------------------------------------------
-// Pilot kernel
+// Pilot kernels
 // ---------------------------------------------------------------------------
+// Weight of sample i: w_i = sqrt(sum_e y_e^2), y_e = I_e / g.  The FP64 value
+// is used when its round-off bound is below 1% of w; otherwise the point is
+// recomputed in double-double (non-finite -> 0).
 template <int N>
-__global__ void __launch_bounds__(BLOCK) k_pilot(PlanDev P, DensityDev D, uint32_t uid, uint64_t seed, uint64_t c0,
-                                                 uint64_t n, double *W) {
+__global__ void __launch_bounds__(BLOCK) k_pilot_w(PlanDev P, DensityDev D, uint32_t uid, uint64_t seed, uint64_t c0,
+                                                   uint64_t n, double *wbuf) {
     constexpr int M = 3 * N - 1, NE = 2 * N - 1;
     __shared__ double vlds[Dims<N>::NV * BLOCK];
+    __shared__ float rlds[Dims<N>::NV * BLOCK];
     uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     double u[2 * M], z[M];
     int path[M];
     uniforms(seed, uid, c0 + i, 2 * M - 1, u);
     SampleOut o = sample_point<M>(D, u, z, path);
-    if (o.ood) return;
-    double I[NE], A[NE];
-    VarsLdsD vars{vlds + threadIdx.x, BLOCK};
-    eval_graph<double, N>(P, z, I, A, vars);
-    double w2 = 0.0;
+    if (o.ood) {
+        wbuf[i] = 0.0;
+        return;
+    }
+    ea I[NE], A[NE];
+    VarsLdsEa vars{vlds + threadIdx.x, rlds + threadIdx.x, BLOCK};
+    eval_graph<ea, N>(P, z, I, A, vars);
+    double w2 = 0.0, r = 0.0;
     for (int e = 0; e < NE; ++e) {
-        double y = ldexp(I[e] / o.gx, -o.gj);
+        double y = ldexp(I[e].v / o.gx, -o.gj);
         w2 += y * y;
+        r += KAPPA * 0x1p-53 * ldexp(I[e].a / o.gx, -o.gj);
     }
     double w = sqrt(w2);
-    if (!isfinite(w)) return;
+    if (!(r <= 0.01 * w) || !isfinite(w)) {
+        dd Id[NE], Ad[NE];
+        VarsPriv<dd, Dims<N>::NV> vd;
+        eval_graph<dd, N>(P, z, Id, Ad, vd);
+        w2 = 0.0;
+        for (int e = 0; e < NE; ++e) {
+            double y = ldexp(to_double(Id[e]) / o.gx, -o.gj);
+            w2 += y * y;
+        }
+        w = sqrt(w2);
+        if (!isfinite(w)) w = 0.0;
+    }
+    wbuf[i] = w;
+}
+
+// wref = mean of wbuf[0, n) in a fixed order (one block of 1024 threads).
+__global__ void __launch_bounds__(1024) k_pilot_ref(const double *wbuf, uint64_t n, double *wref) {
+    __shared__ double sh[1024];
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (uint64_t i = t; i < n; i += 1024) s += wbuf[i];
+    sh[t] = s;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    if (t == 0) *wref = n ? sh[0] / (double)n : 0.0;
+}
+
+// Adds the quantised weight q_i = min(w_i / wref, 2^8) * 2^24 (an integer) to
+// Wq(s, j) for every step (s, j) of the sample's sector path.  Integer atomics
+// make the table independent of the order of the additions.
+template <int N>
+__global__ void __launch_bounds__(BLOCK) k_pilot_scatter(DensityDev D, uint32_t uid, uint64_t seed, uint64_t c0,
+                                                         uint64_t n, const double *wbuf, const double *wref,
+                                                         unsigned long long *Wq) {
+    constexpr int M = 3 * N - 1;
+    uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const double ref = *wref;
+    const double w = wbuf[i];
+    if (!(ref > 0.0) || !(w > 0.0)) return;
+    const unsigned long long q = (unsigned long long)(fmin(w / ref, 256.0) * 16777216.0);
+    if (q == 0ull) return;
+    double u[2 * M], z[M];
+    int path[M];
+    uniforms(seed, uid, c0 + i, 2 * M - 1, u);
+    sample_point<M>(D, u, z, path);
     uint32_t s = (1u << M) - 1u;
     for (int l = 0; l < M - 1; ++l) {
-        atomicAdd(&W[(size_t)s * M + path[l]], w);
+        atomicAdd(&Wq[(size_t)s * M + path[l]], q);
         s &= ~(1u << path[l]);
     }
+}
+
+__global__ void k_pilot_table(const unsigned long long *Wq, size_t cells, double *W) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cells) W[i] = (double)Wq[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -368,32 +430,72 @@ void mlp_free(MlpState &m) {
 extern "C" {
 
 int amm_pilot(amm_ctx *c, uint64_t seed, uint64_t n, int gb, int ge, void *stream) {
-    if (!c || gb < 0 || ge > (int)c->slots.size() || gb >= ge) return fail(AMM_E_ARG, "amm_pilot: bad graph range");
+    if (!c || gb < 0 || ge > (int)c->slots.size() || gb >= ge || n == 0)
+        return fail(AMM_E_ARG, "amm_pilot: bad graph range or sample count");
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(c->device));
+    const uint64_t step = (uint64_t)1 << 23;
+    const uint64_t nbuf = std::min(step, n);
+    double *wbuf = nullptr, *wref = nullptr;
+    unsigned long long *Wq = nullptr;
+    size_t maxcells = 0;
     for (int g = gb; g < ge; ++g) {
+        if (!c->slots[g].built) return fail(AMM_E_NOTBUILT, "amm_pilot: tables not built");
+        maxcells = std::max(maxcells, ((size_t)1 << c->slots[g].M) * c->slots[g].M);
+    }
+    HIPCHK(hipMalloc((void **)&wbuf, nbuf * sizeof(double)));
+    HIPCHK(hipMalloc((void **)&wref, sizeof(double)));
+    HIPCHK(hipMalloc((void **)&Wq, maxcells * sizeof(unsigned long long)));
+    int rc = AMM_OK;
+    for (int g = gb; g < ge && rc == AMM_OK; ++g) {
         GraphSlot &s = c->slots[g];
-        if (!s.built) return fail(AMM_E_NOTBUILT, "amm_pilot: tables not built");
         size_t cells = ((size_t)1 << s.M) * s.M;
-        if (!s.d_pilotW) HIPCHK(hipMalloc((void **)&s.d_pilotW, cells * sizeof(double)));
-        HIPCHK(hipMemsetAsync(s.d_pilotW, 0, cells * sizeof(double), st));
+        if (!s.d_pilotW && hipMalloc((void **)&s.d_pilotW, cells * sizeof(double)) != hipSuccess) {
+            rc = fail(AMM_E_HIP, "amm_pilot: out of device memory");
+            break;
+        }
+        hipMemsetAsync(Wq, 0, cells * sizeof(unsigned long long), st);
         PlanDev P = s.plan_dev();
         DensityDev D = s.dens_dev(false);
-        const uint64_t step = (uint64_t)1 << 26;
         for (uint64_t c0 = 0; c0 < n; c0 += step) {
             uint64_t m = std::min(step, n - c0);
             dim3 gr((unsigned)((m + BLOCK - 1) / BLOCK)), bl(BLOCK);
             switch (s.n) {
-                case 1: hipLaunchKernelGGL(k_pilot<1>, gr, bl, 0, st, P, D, s.uid, seed, c0, m, s.d_pilotW); break;
-                case 2: hipLaunchKernelGGL(k_pilot<2>, gr, bl, 0, st, P, D, s.uid, seed, c0, m, s.d_pilotW); break;
-                case 3: hipLaunchKernelGGL(k_pilot<3>, gr, bl, 0, st, P, D, s.uid, seed, c0, m, s.d_pilotW); break;
-                case 4: hipLaunchKernelGGL(k_pilot<4>, gr, bl, 0, st, P, D, s.uid, seed, c0, m, s.d_pilotW); break;
-                default: return fail(AMM_E_ARG, "amm_pilot: unsupported loop order");
+                case 1: hipLaunchKernelGGL(k_pilot_w<1>, gr, bl, 0, st, P, D, s.uid, seed, c0, m, wbuf); break;
+                case 2: hipLaunchKernelGGL(k_pilot_w<2>, gr, bl, 0, st, P, D, s.uid, seed, c0, m, wbuf); break;
+                case 3: hipLaunchKernelGGL(k_pilot_w<3>, gr, bl, 0, st, P, D, s.uid, seed, c0, m, wbuf); break;
+                case 4: hipLaunchKernelGGL(k_pilot_w<4>, gr, bl, 0, st, P, D, s.uid, seed, c0, m, wbuf); break;
+                default: rc = fail(AMM_E_ARG, "amm_pilot: unsupported loop order");
+            }
+            if (rc) break;
+            if (c0 == 0) hipLaunchKernelGGL(k_pilot_ref, dim3(1), dim3(1024), 0, st, wbuf, m, wref);
+            switch (s.n) {
+                case 1: hipLaunchKernelGGL(k_pilot_scatter<1>, gr, bl, 0, st, D, s.uid, seed, c0, m, wbuf, wref, Wq); break;
+                case 2: hipLaunchKernelGGL(k_pilot_scatter<2>, gr, bl, 0, st, D, s.uid, seed, c0, m, wbuf, wref, Wq); break;
+                case 3: hipLaunchKernelGGL(k_pilot_scatter<3>, gr, bl, 0, st, D, s.uid, seed, c0, m, wbuf, wref, Wq); break;
+                case 4: hipLaunchKernelGGL(k_pilot_scatter<4>, gr, bl, 0, st, D, s.uid, seed, c0, m, wbuf, wref, Wq); break;
             }
         }
-        HIPCHK(hipGetLastError());
+        if (rc) break;
+        hipLaunchKernelGGL(k_pilot_table, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, Wq, cells,
+                           s.d_pilotW);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+            rc = fail(AMM_E_HIP, "amm_pilot: kernel failure");
     }
+    hipStreamSynchronize(st);
+    hipFree(wbuf); hipFree(wref); hipFree(Wq);
     c->last_stream = st;
+    return rc;
+}
+
+int amm_pilot_table(const amm_ctx *c, int g, double *host, size_t cap) {
+    if (!c || g < 0 || g >= (int)c->slots.size() || !host) return fail(AMM_E_ARG, "amm_pilot_table: bad argument");
+    const GraphSlot &s = c->slots[g];
+    size_t cells = ((size_t)1 << s.M) * s.M;
+    if (!s.d_pilotW) return fail(AMM_E_NOTBUILT, "amm_pilot_table: run amm_pilot first");
+    if (cap < cells) return fail(AMM_E_ARG, "amm_pilot_table: buffer too small");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipMemcpy(host, s.d_pilotW, cells * sizeof(double), hipMemcpyDeviceToHost));
     return AMM_OK;
 }
 

@@ -1,0 +1,103 @@
+"""GPU: the learned sector sampler end to end (pilot -> training -> sampling
+with q = (q_theta + g)/2) against the oracle and against the plain density.
+
+The pilot table is integer-valued by construction (quantised weights), so the
+GPU and oracle tables agree up to the per-sample weight error: the GPU weight
+is within 1% of the exact one by its round-off check, and within ~1e-12 in
+practice; both bars are checked."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip('torch')
+pytestmark = pytest.mark.gpu
+
+from oracle import mlp as OM                # noqa: E402
+
+
+@pytest.fixture(scope='module')
+def amm():
+    from paper_1909_08015_amd import Context
+    assert torch.cuda.is_available(), 'GPU tests need a GPU'
+    return Context(0)
+
+
+def test_pilot_table_matches_oracle(amm):
+    n, gi, seed, N = 2, 1, 3, 20000
+    amm.enumerate(n)
+    amm.build_tables()
+    amm.pilot(seed, N, gi, gi + 1)
+    Wg = amm.pilot_table(gi)
+    w, paths = OM.pilot_weights(n, gi, seed, N)
+    Wo = OM.pilot_table(n, gi, seed, N, w, paths)
+    assert np.all(Wg == np.round(Wg)) and Wg.min() >= 0
+    # rigorous: per-sample weight within 1% (+1 for the floor / wref rounding)
+    M = 3 * n - 1
+    wref = w.mean()
+    q = np.floor(np.minimum(w / wref, 256.0) * 16777216.0)
+    tol = np.zeros_like(Wo)
+    full = (1 << M) - 1
+    for i in range(N):
+        s = full
+        for l in range(M - 1):
+            tol[s, paths[i][l]] += 0.011 * q[i] + 2.0
+            s &= ~(1 << int(paths[i][l]))
+    assert np.all(np.abs(Wg - Wo) <= tol)
+    # in practice: relative agreement far below the rigorous bar
+    nz = Wo > 1e6
+    assert np.median(np.abs(Wg[nz] - Wo[nz]) / Wo[nz]) < 1e-8
+    # every sample passes the full set once
+    assert Wg[full].sum() == pytest.approx(q.sum(), rel=1e-9)
+
+
+def test_pilot_is_deterministic(amm):
+    amm.enumerate(3)
+    amm.build_tables()
+    amm.pilot(11, 300000, 0, 2)
+    a = [amm.pilot_table(g) for g in range(2)]
+    amm.pilot(11, 300000, 0, 2)
+    b = [amm.pilot_table(g) for g in range(2)]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def _run(amm, sampler, N, tau, seed=0):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    amm.integrate(seed=seed, n_per_graph=N, sampler=sampler, accept_tau=tau)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    G = amm.n_se
+    est = [amm.read(g, -1) for g in range(G)]
+    return est, dt
+
+
+def test_learned_sampler_unbiased_and_gain(amm):
+    """3-loop set: pilot (seed 1) -> GPU training -> learned mixture on seed 0.
+    Per graph the learned estimate agrees with the plain one within 5 combined
+    sigma; the summed variance times time is reported and must not be worse
+    than the plain density's by more than the 50/50 mixture's worst case."""
+    amm.enumerate(3)
+    amm.build_tables()
+    G = amm.n_se
+    amm.integrate(seed=1, n_per_graph=50_000, force_flag=1)
+    N = 1 << 21
+    tau = amm.accept_thresholds(N)
+    amm.pilot(1, 1_000_000)
+    amm.mlp_train(300, lr=1e-2, init_seed=0)
+    plain, tp = _run(amm, 0, N, tau)
+    learned, tl = _run(amm, 1, N, tau)
+    _run(amm, 0, N, tau)                      # timing after warm caches
+    plain, tp = _run(amm, 0, N, tau)
+    learned, tl = _run(amm, 1, N, tau)
+    for p, l in zip(plain, learned):
+        s = math.sqrt(p['sigma'] ** 2 + l['sigma'] ** 2)
+        assert abs(p['mean'] - l['mean']) <= 5 * s, (p, l)
+    vp = sum(p['sigma'] ** 2 for p in plain)
+    vl = sum(l['sigma'] ** 2 for l in learned)
+    ratio = (vl * tl) / (vp * tp)
+    print(f'\n3-loop sigma^2: plain {vp:.4e} learned {vl:.4e}; time plain {tp:.3f}s learned {tl:.3f}s; '
+          f'sigma^2*time learned/plain = {ratio:.3f}')
+    assert ratio < 2.5

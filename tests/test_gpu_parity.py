@@ -1,6 +1,6 @@
 """GPU parity: the HIP path through the C ABI against the oracle.
 
-Bars (DESIGN.md, reading R14): sample points, densities and sector paths
+Bars (reading R14): sample points, densities and sector paths
 bit-exact on identical Philox streams; per-point integrands within 1e-10 of
 the oracle's exact value relative to max(|I|, sum|terms|) (FP64) and 1e-13
 (double-double); estimates within 1e-3 of the oracle's sigma."""
