@@ -61,7 +61,8 @@ def main():
     ap.add_argument('--gpus', type=int, default=1)
     ap.add_argument('--steps', type=int, default=5)
     ap.add_argument('--warmup', type=int, default=1)
-    ap.add_argument('--batch', type=int, default=1 << 22, help='sample counters per graph per step')
+    ap.add_argument('--batch', type=int, default=3_276_800,
+                    help='sample counters per graph per step (10 x 3276800 = one group of 32000 chunks)')
     ap.add_argument('--pilot', type=int, default=100_000, help='double-double pilot samples per graph')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     args = ap.parse_args()

@@ -22,7 +22,7 @@ int fail(int code, const std::string &msg);
 constexpr int BLOCK = 128;
 constexpr int RPC = 8;                        // rounds per chunk
 constexpr int CHUNK = BLOCK * RPC;            // samples per chunk (the unit of the fixed-order sums)
-constexpr int MAX_CHUNKS_PER_LAUNCH = 8192;   // 8.4M samples per launch
+constexpr int MAX_GROUP_CHUNKS = 32768;       // chunks per group (33.5M samples): one DD pass each
 constexpr int DD_BLOCK = 64;                  // one wave per block in the double-double recompute
 constexpr uint32_t FLAG_DDFAIL = 0x80000000u; // flag word: the DD bound cannot pass either
 constexpr double KAPPA = 64.0;                // round-off bound multiplier (reading R11)
@@ -78,13 +78,17 @@ struct amm_ctx {
     uint32_t *d_flag = nullptr;         // flagged offsets [MAX_CHUNKS * CHUNK]
     int32_t *d_nflag = nullptr;         // per chunk
     int32_t *d_foff = nullptr;          // exclusive scan of d_nflag [MAX_CHUNKS + 1]
-    double *d_ydd = nullptr;            // DD results of flagged points, [ne][MAX_CHUNKS * CHUNK]
+    double *d_ydd = nullptr;            // DD results of flagged points, [ne][MAX_GROUP_CHUNKS * CHUNK]
     int ydd_ne = 0;
+    void *d_segs = nullptr;             // segment tables of one call (SegDev), device
+    void *h_segs = nullptr;             // pinned staging copy
+    size_t seg_cap = 0;                 // capacity in segments
+    hipEvent_t seg_ev = nullptr;        // recorded after the last staging copy
     amm::MlpState mlp;
     bool use_gen = true;                // generated integrand code when built
     // profiling
     bool prof = false;
-    struct Ev { hipEvent_t a, b, c, d; int64_t samples; };
+    struct Ev { hipEvent_t a, b, c, d; int64_t samples; int nseg; };
     std::vector<Ev> evs;
     double prof_ms[3] = {0, 0, 0};
     int64_t prof_launch = 0, prof_samples = 0;

@@ -41,6 +41,9 @@ amm_ctx::~amm_ctx() {
         hipFree(s.d_ptheta); hipFree(s.d_pilotW);
     }
     hipFree(d_acc); hipFree(d_part); hipFree(d_flag); hipFree(d_nflag); hipFree(d_foff); hipFree(d_ydd);
+    hipFree(d_segs);
+    if (seg_ev) hipEventSynchronize(seg_ev), hipEventDestroy(seg_ev);
+    hipHostFree(h_segs);
     mlp_free(mlp);
 }
 
@@ -116,20 +119,26 @@ void launch_eval(const GraphSlot &gs, int g, const double *z, uint64_t n, double
 
 constexpr int DD_GRID = 4096;                 // blocks of the per-point DD recompute (grid-stride)
 
+// FP64 pass of one segment into the group buffers at its chunk offset.
 template <int N>
-void launch_run(const GraphSlot &gs, int g, const DensityDev &D, const RunArgs &A, int grid, amm_ctx *c, hipStream_t s,
-                amm_ctx::Ev *ev, bool use_gen) {
-    InterpEval EV{gs.plan_dev()};
-    if (ev) hipEventRecord(ev->a, s);
-    if (use_gen && gen_launch(N, g))
-        gen_launch(N, g)(GEN_RUN, &D, &A, grid, nullptr, 0, nullptr, nullptr, nullptr, s, c->d_part, c->d_flag,
-                         c->d_nflag);
+void launch_seg_fp64(const GraphSlot &gs, const SegDev &S, int grid, amm_ctx *c, hipStream_t s, bool use_gen) {
+    double *part = c->d_part + (size_t)S.gchunk * NSTAT_MAX;
+    uint32_t *flag = c->d_flag + (size_t)S.gchunk * CHUNK;
+    int32_t *nflag = c->d_nflag + S.gchunk;
+    if (use_gen && gen_launch(N, S.g))
+        gen_launch(N, S.g)(GEN_RUN, &S.D, &S.A, grid, nullptr, 0, nullptr, nullptr, nullptr, s, part, flag, nflag);
     else
-        launch_fp64_ev<N>(EV, D, A, grid, c->d_part, c->d_flag, c->d_nflag, s);
-    if (ev) hipEventRecord(ev->b, s);
-    launch_dd<N>(gs.plan_dev(), D, A, DD_GRID, std::min(A.nchunks, grid), c->d_part, c->d_flag, c->d_nflag, c->d_foff,
-                 c->d_ydd, (size_t)MAX_CHUNKS_PER_LAUNCH * CHUNK, s);
+        launch_fp64_ev<N>(InterpEval{gs.plan_dev()}, S.D, S.A, grid, part, flag, nflag, s);
+}
+
+// DD pass and reduction of one group (segments [k0, k1) of the staged table).
+template <int N>
+void launch_group_tail(amm_ctx *c, const SegDev *d_segs, int nseg, int nch, int grid_red, hipStream_t s,
+                       amm_ctx::Ev *ev) {
+    launch_dd_group<N>(d_segs, nseg, nch, DD_GRID, grid_red, c->d_part, c->d_flag, c->d_nflag, c->d_foff, c->d_ydd,
+                       (size_t)MAX_GROUP_CHUNKS * CHUNK, s);
     if (ev) hipEventRecord(ev->c, s);
+    hipLaunchKernelGGL(k_reduce_seg, dim3(NSTAT_MAX, nseg), dim3(256), 0, s, d_segs, c->d_part, c->d_acc);
 }
 
 void prof_collect(amm_ctx *c) {
@@ -140,7 +149,7 @@ void prof_collect(amm_ctx *c) {
         hipEventElapsedTime(&t2, e.b, e.c);
         hipEventElapsedTime(&t3, e.c, e.d);
         c->prof_ms[0] += t1; c->prof_ms[1] += t2; c->prof_ms[2] += t3;
-        c->prof_launch += 1;
+        c->prof_launch += e.nseg;
         c->prof_samples += e.samples;
         hipEventDestroy(e.a); hipEventDestroy(e.b); hipEventDestroy(e.c); hipEventDestroy(e.d);
     }
@@ -164,10 +173,11 @@ int amm_create(amm_ctx **out, int device) {
     HIPCHK(hipSetDevice(device));
     std::unique_ptr<amm_ctx> c(new amm_ctx);
     c->device = device;
-    HIPCHK(hipMalloc((void **)&c->d_part, (size_t)MAX_CHUNKS_PER_LAUNCH * NSTAT_MAX * sizeof(double)));
-    HIPCHK(hipMalloc((void **)&c->d_flag, (size_t)MAX_CHUNKS_PER_LAUNCH * CHUNK * sizeof(uint32_t)));
-    HIPCHK(hipMalloc((void **)&c->d_nflag, (size_t)MAX_CHUNKS_PER_LAUNCH * sizeof(int32_t)));
-    HIPCHK(hipMalloc((void **)&c->d_foff, (size_t)(MAX_CHUNKS_PER_LAUNCH + 1) * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void **)&c->d_part, (size_t)MAX_GROUP_CHUNKS * NSTAT_MAX * sizeof(double)));
+    HIPCHK(hipMalloc((void **)&c->d_flag, (size_t)MAX_GROUP_CHUNKS * CHUNK * sizeof(uint32_t)));
+    HIPCHK(hipMalloc((void **)&c->d_nflag, (size_t)MAX_GROUP_CHUNKS * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void **)&c->d_foff, (size_t)(MAX_GROUP_CHUNKS + 1) * sizeof(int32_t)));
+    HIPCHK(hipEventCreateWithFlags(&c->seg_ev, hipEventDisableTiming));
     *out = c.release();
     return AMM_OK;
 }
@@ -185,6 +195,7 @@ int amm_enumerate(amm_ctx *c, int loops, int *n_se, int *n_vertex, int *M) {
             hipFree(s.d_ptheta); hipFree(s.d_pilotW);
         }
         c->slots.clear();
+        mlp_free_rows(c->mlp);               // feature rows belong to the old graph set
         c->graphs = enumerate_se(loops);
         c->loops = loops;
         c->slots.resize(c->graphs.size());
@@ -231,6 +242,11 @@ int amm_build_tables(amm_ctx *c, const amm_density_params *params, int gb, int g
         }
         s.n = G.n; s.M = 3 * G.n - 1; s.ne = 2 * G.n - 1;
         s.uid = (uint32_t)((G.n << 20) | g);
+        if (g < (int)c->mlp.rows.size() && c->mlp.rows[g].built) {   // features depend on the density tables
+            MlpRows &R = c->mlp.rows[g];
+            hipFree(R.d_feat); hipFree(R.d_s); hipFree(R.d_j); hipFree(R.d_grp); hipFree(R.d_goff);
+            R = MlpRows();
+        }
         // classes
         std::vector<std::array<int, 3>> ucls;
         for (int e = 0; e < s.ne; ++e) {
@@ -324,65 +340,120 @@ int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
     if (!c || !r) return fail(AMM_E_ARG, "amm_integrate: bad argument");
     if (r->graph_begin < 0 || r->graph_end > (int)c->slots.size() || r->graph_begin >= r->graph_end)
         return fail(AMM_E_ARG, "amm_integrate: bad graph range");
+    for (int g = r->graph_begin; g < r->graph_end; ++g)
+        if (!c->slots[g].built) return fail(AMM_E_NOTBUILT, "amm_integrate: tables not built");
+    if (c->loops < 1 || c->loops > 4) return fail(AMM_E_ARG, "amm_integrate: unsupported loop order");
+    if (c->loops == 1 && r->force_flag)
+        return fail(AMM_E_ARG, "amm_integrate: double-double recompute is disabled at 1 loop (force_flag)");
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(c->device));
     int dev_cus = 256;
     hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device);
     const int ne_ctx = 2 * c->loops - 1;
-    if (c->ydd_ne < ne_ctx) {                 // DD results of up to one launch of samples
+    if (c->ydd_ne < ne_ctx) {                 // DD results of up to one group of samples
         HIPCHK(hipFree(c->d_ydd));
         c->d_ydd = nullptr;
         c->ydd_ne = 0;
-        HIPCHK(hipMalloc((void **)&c->d_ydd, (size_t)ne_ctx * MAX_CHUNKS_PER_LAUNCH * CHUNK * sizeof(double)));
+        HIPCHK(hipMalloc((void **)&c->d_ydd, (size_t)ne_ctx * MAX_GROUP_CHUNKS * CHUNK * sizeof(double)));
         c->ydd_ne = ne_ctx;
     }
+    // Segments: each graph's chunk range cut into pieces of at most one group;
+    // groups: consecutive segments of distinct graphs, at most MAX_GROUP_CHUNKS.
+    const uint64_t nchunks_total = (r->n_per_graph + CHUNK - 1) / CHUNK;
+    std::vector<SegDev> segs;
+    std::vector<int> group_begin;             // first segment of each group
+    int gch = MAX_GROUP_CHUNKS, last_g = -1;
     for (int g = r->graph_begin; g < r->graph_end; ++g) {
         GraphSlot &s = c->slots[g];
-        if (!s.built) return fail(AMM_E_NOTBUILT, "amm_integrate: tables not built");
-        if (!r->accumulate)
-            hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, c->d_acc + (size_t)g * NSTAT_MAX, NSTAT_MAX);
         bool learned = r->sampler == 1 && s.d_ptheta != nullptr;
-        PlanDev P = s.plan_dev();
-        DensityDev D = s.dens_dev(learned);
-        RunArgs A;
-        A.seed = r->seed;
-        A.begin = r->counter0;
-        A.end = r->counter0 + r->n_per_graph;
-        A.uid = s.uid;
-        A.ncls = s.ncls;
-        for (int e = 0; e < MAXNE; ++e) A.cls_of[e] = e < s.ne ? s.cls_of[e] : 0;
-        A.learned = learned ? 1 : 0;
-        if (r->force_flag) A.tau = -1.0;
-        else if (r->accept_tau) A.tau = r->accept_tau[g - r->graph_begin];
-        else A.tau = INFINITY;
-        uint64_t nchunks_total = (r->n_per_graph + CHUNK - 1) / CHUNK;
-        int grid_target = r->samples_per_thread > 0 ? r->samples_per_thread * dev_cus : 8 * dev_cus;
-        for (uint64_t ch0 = 0; ch0 < nchunks_total; ch0 += MAX_CHUNKS_PER_LAUNCH) {
-            int nch = (int)std::min<uint64_t>(MAX_CHUNKS_PER_LAUNCH, nchunks_total - ch0);
-            A.chunk0 = (int)ch0;
-            A.nchunks = nch;
-            int grid = std::min(nch, grid_target);
-            amm_ctx::Ev ev, *evp = nullptr;
-            if (c->prof) {
-                HIPCHK(hipEventCreate(&ev.a)); HIPCHK(hipEventCreate(&ev.b));
-                HIPCHK(hipEventCreate(&ev.c)); HIPCHK(hipEventCreate(&ev.d));
-                uint64_t lo = ch0 * CHUNK, hi = std::min<uint64_t>((ch0 + nch) * CHUNK, r->n_per_graph);
-                ev.samples = (int64_t)(hi - lo);
-                evp = &ev;
+        for (uint64_t ch0 = 0; ch0 < nchunks_total; ch0 += MAX_GROUP_CHUNKS) {
+            int nch = (int)std::min<uint64_t>(MAX_GROUP_CHUNKS, nchunks_total - ch0);
+            if (gch + nch > MAX_GROUP_CHUNKS || last_g == g) {
+                group_begin.push_back((int)segs.size());
+                gch = 0;
             }
-            switch (s.n) {
-                case 1: launch_run<1>(s, g, D, A, grid, c, st, evp, c->use_gen); break;
-                case 2: launch_run<2>(s, g, D, A, grid, c, st, evp, c->use_gen); break;
-                case 3: launch_run<3>(s, g, D, A, grid, c, st, evp, c->use_gen); break;
-                case 4: launch_run<4>(s, g, D, A, grid, c, st, evp, c->use_gen); break;
-                default: return fail(AMM_E_ARG, "amm_integrate: unsupported loop order");
+            SegDev S;
+            std::memset(&S, 0, sizeof(S));
+            S.A.seed = r->seed;
+            S.A.begin = r->counter0;
+            S.A.end = r->counter0 + r->n_per_graph;
+            S.A.uid = s.uid;
+            S.A.chunk0 = (int)ch0;
+            S.A.nchunks = nch;
+            S.A.ncls = s.ncls;
+            for (int e = 0; e < MAXNE; ++e) S.A.cls_of[e] = e < s.ne ? s.cls_of[e] : 0;
+            S.A.learned = learned ? 1 : 0;
+            if (r->force_flag) S.A.tau = -1.0;
+            else if (r->accept_tau) S.A.tau = r->accept_tau[g - r->graph_begin];
+            else S.A.tau = INFINITY;
+            S.P = s.plan_dev();
+            S.D = s.dens_dev(learned);
+            S.g = g;
+            S.nst = s.nstat();
+            S.gchunk = gch;
+            segs.push_back(S);
+            gch += nch;
+            last_g = g;
+        }
+    }
+    group_begin.push_back((int)segs.size());
+    // stage the table: wait until the previous call's copy has been consumed
+    HIPCHK(hipEventSynchronize(c->seg_ev));
+    if (segs.size() > c->seg_cap) {
+        HIPCHK(hipFree(c->d_segs));
+        HIPCHK(hipHostFree(c->h_segs));
+        c->d_segs = c->h_segs = nullptr;
+        c->seg_cap = 0;
+        size_t cap = std::max<size_t>(segs.size(), 256);
+        HIPCHK(hipMalloc(&c->d_segs, cap * sizeof(SegDev)));
+        HIPCHK(hipHostMalloc(&c->h_segs, cap * sizeof(SegDev)));
+        c->seg_cap = cap;
+    }
+    std::memcpy(c->h_segs, segs.data(), segs.size() * sizeof(SegDev));
+    HIPCHK(hipMemcpyAsync(c->d_segs, c->h_segs, segs.size() * sizeof(SegDev), hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(c->seg_ev, st));
+    const SegDev *d_segs = (const SegDev *)c->d_segs;
+    if (!r->accumulate)
+        for (int g = r->graph_begin; g < r->graph_end; ++g)
+            hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, c->d_acc + (size_t)g * NSTAT_MAX, NSTAT_MAX);
+    const int grid_target = r->samples_per_thread > 0 ? r->samples_per_thread * dev_cus : 8 * dev_cus;
+    for (size_t q = 0; q + 1 < group_begin.size(); ++q) {
+        const int k0 = group_begin[q], k1 = group_begin[q + 1];
+        const int nch = segs[k1 - 1].gchunk + segs[k1 - 1].A.nchunks;
+        amm_ctx::Ev ev, *evp = nullptr;
+        if (c->prof) {
+            HIPCHK(hipEventCreate(&ev.a)); HIPCHK(hipEventCreate(&ev.b));
+            HIPCHK(hipEventCreate(&ev.c)); HIPCHK(hipEventCreate(&ev.d));
+            ev.samples = 0;
+            ev.nseg = k1 - k0;
+            for (int k = k0; k < k1; ++k) {
+                uint64_t lo = (uint64_t)segs[k].A.chunk0 * CHUNK;
+                uint64_t hi = std::min<uint64_t>(lo + (uint64_t)segs[k].A.nchunks * CHUNK, r->n_per_graph);
+                ev.samples += (int64_t)(hi - lo);
             }
-            hipLaunchKernelGGL(k_reduce, dim3(s.nstat()), dim3(256), 0, st, c->d_part, nch,
-                               c->d_acc + (size_t)g * NSTAT_MAX);
-            if (evp) {
-                HIPCHK(hipEventRecord(ev.d, st));
-                c->evs.push_back(ev);
+            evp = &ev;
+            HIPCHK(hipEventRecord(ev.a, st));
+        }
+        for (int k = k0; k < k1; ++k) {
+            const int grid = std::min(segs[k].A.nchunks, grid_target);
+            switch (c->loops) {
+                case 1: launch_seg_fp64<1>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
+                case 2: launch_seg_fp64<2>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
+                case 3: launch_seg_fp64<3>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
+                case 4: launch_seg_fp64<4>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
             }
+        }
+        if (evp) HIPCHK(hipEventRecord(ev.b, st));
+        const int grid_red = std::min(nch, grid_target);
+        switch (c->loops) {
+            case 1: launch_group_tail<1>(c, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
+            case 2: launch_group_tail<2>(c, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
+            case 3: launch_group_tail<3>(c, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
+            case 4: launch_group_tail<4>(c, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
+        }
+        if (evp) {
+            HIPCHK(hipEventRecord(ev.d, st));
+            c->evs.push_back(ev);
         }
         HIPCHK(hipGetLastError());
     }

@@ -45,6 +45,27 @@ struct RunArgs {
     int learned;
 };
 
+// One segment of a group: graph g's chunks [A.chunk0, A.chunk0 + A.nchunks)
+// of its sample range, stored at chunks [gchunk, gchunk + A.nchunks) of the
+// group's buffers.
+struct SegDev {
+    RunArgs A;
+    PlanDev P;
+    DensityDev D;
+    int g, nst, gchunk, pad;
+};
+
+// Segment holding group chunk ch (segments sorted by gchunk).
+__device__ __forceinline__ int seg_of_chunk(const SegDev *segs, int nseg, int ch) {
+    int lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (segs[mid].gchunk <= ch) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // T = ea: FP64 value with its round-off bound KAPPA u I.a; T = dd: double-double.
 template <typename T, int N, class Ev>
 __global__ void __launch_bounds__(BLOCK) k_eval(Ev EV, const double *z, uint64_t n, double *I, double *absI,
@@ -127,6 +148,7 @@ __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, c
                 y[e] = ldexp(I[e] / o.gx, -o.gj);
                 if (!isfinite(y[e])) flag = 1;
             }
+            if constexpr (N == 1) ddbad = flag;
         }
     } else {
         ea I[NE], aI[NE];
@@ -142,6 +164,7 @@ __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, c
             double r = ldexp(I[e].a / o.gx, -o.gj);
             if (!(KAPPA * 0x1p-53 * r <= A.tau) || !isfinite(ye)) flag = 1;
             if (A.tau >= 0.0 && !(KAPPA * 0x1p-104 * r <= A.tau)) ddbad = 1;
+            if constexpr (N == 1) ddbad = 1;        // no double-double recompute at one loop (disabled)
             y[e] = ye;
         }
     }
@@ -222,9 +245,9 @@ __global__ void __launch_bounds__(BLOCK) k_integrate(Ev EV, DensityDev D, RunArg
 }
 
 // Exclusive scan of the per-chunk flag counts (one block of 1024 threads;
-// nchunks <= MAX_CHUNKS_PER_LAUNCH): off[0..nchunks], off[nchunks] = total.
+// nchunks <= MAX_GROUP_CHUNKS): off[0..nchunks], off[nchunks] = total.
 static __global__ void __launch_bounds__(1024) k_flag_scan(const int32_t *nflag, int nchunks, int32_t *off) {
-    constexpr int T = 1024, PER = (MAX_CHUNKS_PER_LAUNCH + T - 1) / T;
+    constexpr int T = 1024, PER = (MAX_GROUP_CHUNKS + T - 1) / T;
     __shared__ int32_t sh[T];
     const int t = threadIdx.x;
     int32_t loc[PER], s = 0;
@@ -260,14 +283,14 @@ struct VarsLdsDd {
 };
 
 // Double-double recompute, one flagged sample per thread over the whole
-// launch: y_e of flagged point f goes to ydd[e * cap + f]; a point that fails
-// (bound, or a non-finite value) gets NaN in ydd[f].
+// group: y_e of flagged point f goes to ydd[e * cap + f]; a point that fails
+// (bound, or a non-finite value) gets NaN in ydd[f].  Points are in chunk
+// order, so the lanes of a wave nearly always share a graph's tables.
 template <int N>
-__global__ void __launch_bounds__(DD_BLOCK) k_dd_points(PlanDev P, DensityDev D, RunArgs A, const uint32_t *flags,
+__global__ void __launch_bounds__(DD_BLOCK) k_dd_points(const SegDev *segs, int nseg, int nch, const uint32_t *flags,
                                                         const int32_t *off, double *ydd, size_t cap) {
     constexpr int M = 3 * N - 1, NE = 2 * N - 1;
     __shared__ double vh[Dims<N>::NV * DD_BLOCK], vl[Dims<N>::NV * DD_BLOCK];
-    const int nch = A.nchunks;
     const int32_t total = off[nch];
     for (int32_t f = blockIdx.x * DD_BLOCK + threadIdx.x; f < total; f += gridDim.x * DD_BLOCK) {
         int lo = 0, hi = nch;                 // largest chunk with off[chunk] <= f
@@ -276,18 +299,19 @@ __global__ void __launch_bounds__(DD_BLOCK) k_dd_points(PlanDev P, DensityDev D,
             if (off[mid] <= f) lo = mid;
             else hi = mid;
         }
+        const SegDev &S = segs[seg_of_chunk(segs, nseg, lo)];
         const uint32_t w = flags[(size_t)lo * CHUNK + (f - off[lo])];
         bool fail = (w & FLAG_DDFAIL) != 0u;
         double y[NE];
         if (!fail) {
-            uint64_t idx = A.begin + (uint64_t)(A.chunk0 + lo) * CHUNK + (w & ~FLAG_DDFAIL);
+            uint64_t idx = S.A.begin + (uint64_t)(S.A.chunk0 + (lo - S.gchunk)) * CHUNK + (w & ~FLAG_DDFAIL);
             double u[2 * M], z[M];
             int path[M];
-            uniforms(A.seed, A.uid, idx, D.ptheta ? 2 * M : 2 * M - 1, u);
-            SampleOut o = sample_point<M>(D, u, z, path);
+            uniforms(S.A.seed, S.A.uid, idx, S.D.ptheta ? 2 * M : 2 * M - 1, u);
+            SampleOut o = sample_point<M>(S.D, u, z, path);
             dd I[NE], aI[NE];
             VarsLdsDd vars{vh + threadIdx.x, vl + threadIdx.x, DD_BLOCK};
-            eval_graph<dd, N>(P, z, I, aI, vars);
+            eval_graph<dd, N>(S.P, z, I, aI, vars);
             for (int e = 0; e < NE; ++e) {
                 y[e] = ldexp(to_double(I[e]) / o.gx, -o.gj);
                 if (!isfinite(y[e])) fail = true;
@@ -303,15 +327,16 @@ __global__ void __launch_bounds__(DD_BLOCK) k_dd_points(PlanDev P, DensityDev D,
 
 // Adds the recomputed samples of each chunk to its partial sums, in flag order.
 template <int N>
-__global__ void __launch_bounds__(BLOCK) k_dd_reduce(RunArgs A, const int32_t *off, const double *ydd, size_t cap,
-                                                     double *part) {
+__global__ void __launch_bounds__(BLOCK) k_dd_reduce(const SegDev *segs, int nseg, int nch, const int32_t *off,
+                                                     const double *ydd, size_t cap, double *part) {
     constexpr int NE = 2 * N - 1;
     constexpr int NST = 3 * NE + 2 * NE + 4;
     __shared__ double shs[BLOCK / 64][NST];
-    const int nst = 3 * NE + 2 * A.ncls + 4;
-    for (int ch = blockIdx.x; ch < A.nchunks; ch += gridDim.x) {
+    for (int ch = blockIdx.x; ch < nch; ch += gridDim.x) {
         const int32_t a = off[ch], b = off[ch + 1];
         if (a == b) continue;                 // uniform over the block
+        const RunArgs &A = segs[seg_of_chunk(segs, nseg, ch)].A;
+        const int nst = 3 * NE + 2 * A.ncls + 4;
         double st[NST];
         for (int s = 0; s < NST; ++s) st[s] = 0.0;
         for (int32_t f = a + threadIdx.x; f < b; f += BLOCK) {
@@ -328,6 +353,24 @@ __global__ void __launch_bounds__(BLOCK) k_dd_reduce(RunArgs A, const int32_t *o
     }
 }
 
+// acc[g][s] += sum over the segment's chunks of part[chunk][s]: block
+// (s, segment); thread t sums chunks t, t+256, ... in order, then a fixed tree.
+static __global__ void __launch_bounds__(256) k_reduce_seg(const SegDev *segs, const double *part, double *acc) {
+    __shared__ double sh[256];
+    const SegDev &S = segs[blockIdx.y];
+    const int s = blockIdx.x, t = threadIdx.x;
+    if (s >= S.nst) return;                   // uniform over the block
+    double v = 0.0;
+    for (int c = t; c < S.A.nchunks; c += 256) v += part[(size_t)(S.gchunk + c) * NSTAT_MAX + s];
+    sh[t] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    if (t == 0) acc[(size_t)S.g * NSTAT_MAX + s] += sh[0];
+}
+
 // Launch the FP64 pass of one chunk batch.
 template <int N, class Ev>
 void launch_fp64_ev(const Ev &EV, const DensityDev &D, const RunArgs &A, int grid, double *part, uint32_t *flag,
@@ -335,14 +378,15 @@ void launch_fp64_ev(const Ev &EV, const DensityDev &D, const RunArgs &A, int gri
     hipLaunchKernelGGL((k_integrate<N, Ev>), dim3(grid), dim3(BLOCK), 0, s, EV, D, A, part, flag, nflag);
 }
 
-// Launch the double-double recompute of the flagged samples of a chunk batch
-// (scan, per-point recompute, per-chunk sums).
+// Double-double recompute of the flagged samples of a group (scan, per-point
+// recompute, per-chunk sums), then the per-segment reduction into the graph
+// accumulators.
 template <int N>
-void launch_dd(const PlanDev &P, const DensityDev &D, const RunArgs &A, int grid_pts, int grid_red, double *part,
-               const uint32_t *flag, const int32_t *nflag, int32_t *off, double *ydd, size_t cap, hipStream_t s) {
-    hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, s, nflag, A.nchunks, off);
-    hipLaunchKernelGGL((k_dd_points<N>), dim3(grid_pts), dim3(DD_BLOCK), 0, s, P, D, A, flag, off, ydd, cap);
-    hipLaunchKernelGGL((k_dd_reduce<N>), dim3(grid_red), dim3(BLOCK), 0, s, A, off, ydd, cap, part);
+void launch_dd_group(const SegDev *d_segs, int nseg, int nch, int grid_pts, int grid_red, double *part,
+                     const uint32_t *flag, const int32_t *nflag, int32_t *off, double *ydd, size_t cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, s, nflag, nch, off);
+    hipLaunchKernelGGL((k_dd_points<N>), dim3(grid_pts), dim3(DD_BLOCK), 0, s, d_segs, nseg, nch, flag, off, ydd, cap);
+    hipLaunchKernelGGL((k_dd_reduce<N>), dim3(grid_red), dim3(BLOCK), 0, s, d_segs, nseg, nch, off, ydd, cap, part);
 }
 
 template <int N, class Ev, typename T>

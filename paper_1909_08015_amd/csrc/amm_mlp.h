@@ -33,5 +33,6 @@ struct MlpState {
 };
 
 void mlp_free(MlpState &m);
+void mlp_free_rows(MlpState &m);   // drop the per-graph feature rows (graph set changed)
 
 }  // namespace amm

@@ -417,13 +417,17 @@ int loss_grad(amm_ctx *c, const float *X, const float *w, const int32_t *goff, i
 }  // namespace
 
 namespace amm {
-void mlp_free(MlpState &m) {
-    hipFree(m.d_params); hipFree(m.d_m); hipFree(m.d_v);
-    m.d_params = m.d_m = m.d_v = nullptr;
+void mlp_free_rows(MlpState &m) {
     for (auto &r : m.rows) {
         hipFree(r.d_feat); hipFree(r.d_s); hipFree(r.d_j); hipFree(r.d_grp); hipFree(r.d_goff);
     }
     m.rows.clear();
+}
+
+void mlp_free(MlpState &m) {
+    hipFree(m.d_params); hipFree(m.d_m); hipFree(m.d_v);
+    m.d_params = m.d_m = m.d_v = nullptr;
+    mlp_free_rows(m);
 }
 }  // namespace amm
 
