@@ -37,7 +37,7 @@ def cpu_baseline(seconds_target=15.0):
     E.run(3, 0, 0, 0, n, chunk=n)
     dt = time.perf_counter() - t0
     reps = max(1, int(seconds_target / max(dt, 1e-3)))
-    reps = min(reps, 20)
+    reps = min(reps, 2000)
     t0 = time.perf_counter()
     E.run(3, 0, 0, 0, n * reps, chunk=n)
     dt = time.perf_counter() - t0
