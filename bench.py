@@ -56,6 +56,68 @@ def cpu_baseline(seconds_target=15.0):
             "seconds": dt}
 
 
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def learned_vs_plain(ctx, tau, n):
+    """sigma^2 * time of the learned mixture against the plain density on the
+    3-loop set: pilot (seed 1, 1e6 samples per graph) -> MLP training on the
+    GPU -> n samples per graph of each sampler on seed 0; sigma^2 summed over
+    graphs (per graph the sum of its class variances)."""
+    import torch
+    G = ctx.n_se
+    t_pilot = _timed(torch, lambda: ctx.pilot(1, 1_000_000))
+    t_train = _timed(torch, lambda: ctx.mlp_train(300, lr=1e-2, init_seed=0))
+    res = {}
+    for name, smp in (('plain', 0), ('learned', 1)):
+        ctx.integrate(seed=0, n_per_graph=n, sampler=smp, accept_tau=tau)          # warm
+        dt = _timed(torch, lambda: ctx.integrate(seed=0, n_per_graph=n, sampler=smp, accept_tau=tau))
+        var = sum(ctx.read(g, -1)['sigma'] ** 2 for g in range(G))
+        res[name] = (var, dt)
+    (vp, tp), (vl, tl) = res['plain'], res['learned']
+    return {"sigma2_time_ratio_learned_over_plain": (vl * tl) / (vp * tp), "var_plain": vp, "var_learned": vl,
+            "s_plain": tp, "s_learned": tl, "samples_per_graph": n, "pilot_samples_per_graph": 1_000_000,
+            "pilot_s": t_pilot, "train_epochs": 300, "train_s": t_train, "loops": 3}
+
+
+def other_loop_orders(ctx, args):
+    """Samples/s and FP64 fraction of peak at 1, 2 (generated code) and 4
+    loops (74 graphs, table interpreter, one persistent launch per group,
+    autotuned launch configuration)."""
+    import torch
+    out = {}
+    for n, per_graph in ((1, 1 << 24), (2, 1 << 23), (4, 1 << 16)):
+        ctx.enumerate(n)
+        t_build = _timed(torch, lambda: ctx.build_tables())
+        G = ctx.n_se
+        flops = sum(ctx.plan_stats(g)['flops_per_sample'] for g in range(G))
+        tau = None
+        if n > 1:
+            ctx.integrate(seed=1, n_per_graph=10_000 if n == 4 else 100_000, force_flag=1)
+            tau = ctx.accept_thresholds(10 ** 10 // G if n == 4 else 10 ** 7)
+        tune = None
+        if n == 4:
+            tune = ctx.autotune(seed=0, n_per_graph=8192, accept_tau=tau)
+        ctx.integrate(seed=0, n_per_graph=per_graph // 4, accept_tau=tau)               # warm
+        ctx.profile(True)
+        dt = _timed(torch, lambda: ctx.integrate(seed=0, n_per_graph=per_graph, accept_tau=tau))
+        prof = ctx.profile(False)
+        est = ctx.read(-1, -1, None)
+        achieved = flops * per_graph / (prof['ms_fp64'] * 1e-3)
+        out[str(n)] = {"graphs": G, "samples_per_graph": per_graph, "samples_per_s": G * per_graph / dt,
+                       "fp64_pass_ms": prof['ms_fp64'], "dd_ms": prof['ms_dd'],
+                       "fp64_tflops": achieved / 1e12, "fp64_frac_of_peak": achieved / PEAK_FP64_VALU,
+                       "flag_rate": est['n_flag'] / max(est['n'], 1), "n_dd_fail": est['n_dd_fail'],
+                       "tables_build_s": t_build, "autotune": tune,
+                       "evaluator": "generated" if n < 4 else "interpreter, fused persistent launch"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -65,6 +127,8 @@ def main():
                     help='sample counters per graph per step (10 x 3276800 = one group of 32000 chunks)')
     ap.add_argument('--pilot', type=int, default=100_000, help='double-double pilot samples per graph')
     ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--no-learned', action='store_true', help='skip the learned-sampler sigma^2*time measurement')
+    ap.add_argument('--no-other-orders', action='store_true', help='skip the 1-, 2- and 4-loop measurements')
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) != 1:
         print('bench.py: this build runs on one GPU only; multi-GPU runs are not part of it '
@@ -131,6 +195,17 @@ def main():
                                   "n_flag": est['n_flag'], "n_dd_fail": est['n_dd_fail'], "n_ood": est['n_ood']},
         "flag_rate": est['n_flag'] / max(est['n'], 1),
     }
+    # the same steps as captured HIP-graph replays (one capture, `steps` replays)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.integrate_batches(seed=0, n_per_graph=B, n_batches=args.steps, counter0=counter, accumulate=1,
+                          accept_tau=tau)
+    torch.cuda.synchronize()
+    out["graph_replay_samples_per_s"] = args.steps * B * G / (time.perf_counter() - t0)
+    if not args.no_learned:
+        out["learned_vs_plain"] = learned_vs_plain(ctx, tau, B)
+    if not args.no_other_orders:
+        out["other_loop_orders"] = other_loop_orders(ctx, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -60,7 +60,9 @@ typedef struct {
  *                (interval_accept) as a host array of length graph_end -
  *                graph_begin, or NULL for no flagging.
  *   force_flag:  1 = recompute every point in double-double.
- *   samples_per_thread: 0 = autotuned value for the loop order.
+ *   blocks_per_cu: resident blocks per compute unit of the FP64 pass (grid =
+ *                blocks_per_cu x CUs); 0 = the context's value (amm_autotune,
+ *                default 8).  Results do not depend on it.
  *   accumulate:  0 = reset the accumulators of these graphs first. */
 typedef struct {
     uint64_t seed;
@@ -69,7 +71,7 @@ typedef struct {
     int graph_begin, graph_end;
     int sampler;
     int force_flag;
-    int samples_per_thread;
+    int blocks_per_cu;
     int accumulate;
     const double *accept_tau;
 } amm_run_params;
@@ -139,12 +141,44 @@ int amm_eval(amm_ctx *ctx, int g, const double *z, uint64_t n,
  * recompute of flagged points, accumulate) asynchronously on `stream`. */
 int amm_integrate(amm_ctx *ctx, const amm_run_params *run, void *stream);
 
-/* Options.  AMM_OPT_GENERATED (default 1): evaluate integrands with the
- * straight-line code generated at build time for the graph when it exists
- * (1-3 loops), else (0, or no generated code) with the table interpreter.
- * Both compute the same levels and polynomials; results agree to rounding. */
+/* The same run repeated n_batches times as consecutive counter ranges:
+ * batch b evaluates counters counter0 + b*n_per_graph .. + n_per_graph - 1 of
+ * every graph (b = 0 .. n_batches-1), accumulating (accumulate = 0 resets the
+ * accumulators once, before batch 0).  The kernels of one batch (FP64 pass,
+ * double-double recompute, reductions, advance of a device-resident counter
+ * base) are captured once into a HIP graph and replayed; results equal those
+ * of n_batches amm_integrate calls over the same counters.  Synchronises
+ * `stream` (the graph runs on an internal stream ordered after it).
+ * Errors: AMM_E_ARG, AMM_E_NOTBUILT, AMM_E_HIP. */
+int amm_integrate_batches(amm_ctx *ctx, const amm_run_params *run, uint64_t n_batches, void *stream);
+
+/* Options (value semantics per option):
+ * AMM_OPT_GENERATED (default 1): evaluate integrands with the straight-line
+ *   code generated at build time for the graph when it exists (1-3 loops),
+ *   else (0, or no generated code) with the table interpreter.  Both compute
+ *   the same levels and polynomials; results agree to rounding.
+ * AMM_OPT_FUSED (default 1): a group whose graphs all use the interpreter
+ *   runs its FP64 pass as one persistent launch (blocks take chunks from a
+ *   work counter) instead of one launch per graph.
+ * AMM_OPT_ORDER_BY_COST (default 1): order the graphs of a group by plan cost,
+ *   heaviest first (0: graph order).
+ * AMM_OPT_BLOCKS_PER_CU (default 0 = 8): blocks per compute unit of the FP64
+ *   pass when a run does not set its own.
+ * None of them changes results: sums are keyed by 1024-sample chunk. */
 #define AMM_OPT_GENERATED 1
+#define AMM_OPT_FUSED 2
+#define AMM_OPT_ORDER_BY_COST 3
+#define AMM_OPT_BLOCKS_PER_CU 4
 int amm_set_option(amm_ctx *ctx, int option, int value);
+
+/* Launch-configuration autotuner: times the run `run` (its n_per_graph is the
+ * probe size; a warm-up and a timed call per candidate) for blocks per CU in
+ * {1, 2, 4, 8, 16} and both graph orders, keeps the fastest in the context
+ * (AMM_OPT_BLOCKS_PER_CU, AMM_OPT_ORDER_BY_COST) and reports it (host
+ * outputs, may be NULL; ms_best = milliseconds of the best probe).  The
+ * accumulators are restored afterwards.  Synchronises `stream`. */
+int amm_autotune(amm_ctx *ctx, const amm_run_params *run, int *blocks_per_cu, int *order_by_cost,
+                 double *ms_best, void *stream);
 
 /* Round-off acceptance thresholds of eq. (interval_accept), Sec. IV.A:
  * tau_j = (1/4) sigma_j sqrt(sum_l sigma_l^2) / sum_l sigma_l over the graphs

@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, 'libamm.so')
 
 AMM_OK = 0
+OPT_GENERATED, OPT_FUSED, OPT_ORDER_BY_COST, OPT_BLOCKS_PER_CU = 1, 2, 3, 4
 
 
 class AmmError(RuntimeError):
@@ -26,7 +27,7 @@ class DensityParams(C.Structure):
 class RunParams(C.Structure):
     _fields_ = [('seed', C.c_uint64), ('counter0', C.c_uint64), ('n_per_graph', C.c_uint64),
                 ('graph_begin', C.c_int), ('graph_end', C.c_int), ('sampler', C.c_int),
-                ('force_flag', C.c_int), ('samples_per_thread', C.c_int), ('accumulate', C.c_int),
+                ('force_flag', C.c_int), ('blocks_per_cu', C.c_int), ('accumulate', C.c_int),
                 ('accept_tau', C.POINTER(C.c_double))]
 
 
@@ -60,6 +61,9 @@ SYMBOLS = {
     'amm_eval': (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p,
                            C.c_int, C.c_void_p]),
     'amm_integrate': (C.c_int, [C.c_void_p, C.POINTER(RunParams), C.c_void_p]),
+    'amm_integrate_batches': (C.c_int, [C.c_void_p, C.POINTER(RunParams), C.c_uint64, C.c_void_p]),
+    'amm_autotune': (C.c_int, [C.c_void_p, C.POINTER(RunParams), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                               C.POINTER(C.c_double), C.c_void_p]),
     'amm_read': (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Estimate)]),
     'amm_set_option': (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     'amm_accept_thresholds': (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_uint64, C.c_void_p]),
@@ -187,16 +191,39 @@ class Context:
                'amm_eval')
         return (I, A, B) if with_bound else (I, A)
 
-    def integrate(self, seed, n_per_graph, graph_begin=0, graph_end=None, counter0=0, sampler=0,
-                  force_flag=0, samples_per_thread=0, accumulate=0, accept_tau=None, stream=None):
+    def _run_params(self, seed, n_per_graph, graph_begin, graph_end, counter0, sampler, force_flag,
+                    blocks_per_cu, accumulate, accept_tau):
         graph_end = self.n_se if graph_end is None else graph_end
         tau = None
         if accept_tau is not None:
             tau = (C.c_double * len(accept_tau))(*accept_tau)
         rp = RunParams(seed, counter0, n_per_graph, graph_begin, graph_end, sampler, force_flag,
-                       samples_per_thread, accumulate,
+                       blocks_per_cu, accumulate,
                        C.cast(tau, C.POINTER(C.c_double)) if tau is not None else None)
+        return rp, tau
+
+    def integrate(self, seed, n_per_graph, graph_begin=0, graph_end=None, counter0=0, sampler=0,
+                  force_flag=0, blocks_per_cu=0, accumulate=0, accept_tau=None, stream=None):
+        rp, _keep = self._run_params(seed, n_per_graph, graph_begin, graph_end, counter0, sampler, force_flag,
+                                     blocks_per_cu, accumulate, accept_tau)
         _check(lib().amm_integrate(self.h, C.byref(rp), _stream(stream)), 'amm_integrate')
+
+    def integrate_batches(self, seed, n_per_graph, n_batches, graph_begin=0, graph_end=None, counter0=0,
+                          sampler=0, force_flag=0, blocks_per_cu=0, accumulate=0, accept_tau=None, stream=None):
+        rp, _keep = self._run_params(seed, n_per_graph, graph_begin, graph_end, counter0, sampler, force_flag,
+                                     blocks_per_cu, accumulate, accept_tau)
+        _check(lib().amm_integrate_batches(self.h, C.byref(rp), n_batches, _stream(stream)),
+               'amm_integrate_batches')
+
+    def autotune(self, seed, n_per_graph, graph_begin=0, graph_end=None, sampler=0, accept_tau=None, stream=None):
+        rp, _keep = self._run_params(seed, n_per_graph, graph_begin, graph_end, 0, sampler, 0, 0, 0, accept_tau)
+        b, o, ms = C.c_int(), C.c_int(), C.c_double()
+        _check(lib().amm_autotune(self.h, C.byref(rp), C.byref(b), C.byref(o), C.byref(ms), _stream(stream)),
+               'amm_autotune')
+        return dict(blocks_per_cu=b.value, order_by_cost=o.value, ms=ms.value)
+
+    def set_option(self, option, value):
+        _check(lib().amm_set_option(self.h, option, int(value)), 'amm_set_option')
 
     def set_generated(self, on):
         """Use the build-time generated integrand code (True) or the table

@@ -27,7 +27,7 @@ HIP_FLAGS = ['-O3', '-std=c++17', '-fPIC', f'--offload-arch={ARCH}', '-ffp-contr
              '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops',
              '-munsafe-fp-atomics', '-Wno-unused-result', '-Wno-unused-value', '-Wno-unused-variable',
              '-I', CSRC, '-I', GEN]
-HOST_FLAGS = ['-O2', '-std=c++17', '-fPIC', '-ffp-contract=off', '-Wno-unknown-pragmas']
+HOST_FLAGS = ['-O2', '-std=c++17', '-fPIC', '-pthread', '-ffp-contract=off', '-Wno-unknown-pragmas']
 NGRAPHS = {1: 1, 2: 2, 3: 10, 4: 74}
 
 
@@ -63,7 +63,7 @@ def build(verbose=True, jobs=None):
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(compile_one, hip_srcs))
     tmp = OUT + '.tmp'
-    run([hipcc, '-shared', f'--offload-arch={ARCH}', '-o', tmp, host_o] + objs)
+    run([hipcc, '-shared', '-pthread', f'--offload-arch={ARCH}', '-o', tmp, host_o] + objs)
     os.replace(tmp, OUT)
     return OUT
 

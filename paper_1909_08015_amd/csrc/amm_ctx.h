@@ -84,6 +84,13 @@ struct amm_ctx {
     void *h_segs = nullptr;             // pinned staging copy
     size_t seg_cap = 0;                 // capacity in segments
     hipEvent_t seg_ev = nullptr;        // recorded after the last staging copy
+    int *d_work = nullptr;              // work counter of the persistent fused kernel
+    uint64_t *d_base = nullptr;         // sample base added by replays of a captured batch
+    hipStream_t cap_stream = nullptr;   // internal stream for graph capture and replay
+    // launch configuration (set by amm_autotune or amm_set_option)
+    int use_fused = 1;                  // interpreter graphs: one persistent launch per group
+    int order_by_cost = 1;              // segments of a group heaviest graph first
+    int blocks_per_cu = 0;              // 0: default
     amm::MlpState mlp;
     bool use_gen = true;                // generated integrand code when built
     // profiling

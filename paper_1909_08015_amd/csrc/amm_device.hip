@@ -12,9 +12,11 @@
 // the grid size.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <thread>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -41,8 +43,9 @@ amm_ctx::~amm_ctx() {
         hipFree(s.d_ptheta); hipFree(s.d_pilotW);
     }
     hipFree(d_acc); hipFree(d_part); hipFree(d_flag); hipFree(d_nflag); hipFree(d_foff); hipFree(d_ydd);
-    hipFree(d_segs);
+    hipFree(d_segs); hipFree(d_work); hipFree(d_base);
     if (seg_ev) hipEventSynchronize(seg_ev), hipEventDestroy(seg_ev);
+    if (cap_stream) hipStreamSynchronize(cap_stream), hipStreamDestroy(cap_stream);
     hipHostFree(h_segs);
     mlp_free(mlp);
 }
@@ -178,6 +181,8 @@ int amm_create(amm_ctx **out, int device) {
     HIPCHK(hipMalloc((void **)&c->d_nflag, (size_t)MAX_GROUP_CHUNKS * sizeof(int32_t)));
     HIPCHK(hipMalloc((void **)&c->d_foff, (size_t)(MAX_GROUP_CHUNKS + 1) * sizeof(int32_t)));
     HIPCHK(hipEventCreateWithFlags(&c->seg_ev, hipEventDisableTiming));
+    HIPCHK(hipMalloc((void **)&c->d_work, sizeof(int)));
+    HIPCHK(hipMalloc((void **)&c->d_base, sizeof(uint64_t)));
     *out = c.release();
     return AMM_OK;
 }
@@ -231,15 +236,32 @@ int amm_build_tables(amm_ctx *c, const amm_density_params *params, int gb, int g
     if (params) p = *params;
     else p = amm_density_params{0.256, 0.839, 0.786, 0.2, 0.0, 0.2, {((1.0 - 0.03) - 0.01) - 0.06, 0.03, 0.01, 0.06}, 0.75};
     HIPCHK(hipSetDevice(c->device));
+    // host plans and densities: independent per graph, built on a thread pool
+    {
+        std::atomic<int> next(gb);
+        std::vector<std::string> errs(ge - gb);
+        auto work = [&]() {
+            for (int g = next++; g < ge; g = next++) {
+                try {
+                    build_density(c->graphs[g], p, c->slots[g].dens);
+                    build_plan(c->graphs[g], c->slots[g].plan);
+                } catch (const std::exception &ex) {
+                    errs[g - gb] = ex.what();
+                }
+            }
+        };
+        unsigned nt = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 16u));
+        nt = std::min<unsigned>(nt, (unsigned)(ge - gb));
+        std::vector<std::thread> pool;
+        for (unsigned t = 1; t < nt; ++t) pool.emplace_back(work);
+        work();
+        for (auto &th : pool) th.join();
+        for (auto &e : errs)
+            if (!e.empty()) return fail(AMM_E_NUMERIC, std::string("amm_build_tables: ") + e);
+    }
     for (int g = gb; g < ge; ++g) {
         GraphSlot &s = c->slots[g];
         const SEGraph &G = c->graphs[g];
-        try {
-            build_density(G, p, s.dens);
-            build_plan(G, s.plan);
-        } catch (const std::exception &ex) {
-            return fail(AMM_E_NUMERIC, std::string("amm_build_tables: ") + ex.what());
-        }
         s.n = G.n; s.M = 3 * G.n - 1; s.ne = 2 * G.n - 1;
         s.uid = (uint32_t)((G.n << 20) | g);
         if (g < (int)c->mlp.rows.size() && c->mlp.rows[g].built) {   // features depend on the density tables
@@ -336,7 +358,10 @@ int amm_eval(amm_ctx *c, int g, const double *z, uint64_t n, double *I, double *
     return AMM_OK;
 }
 
-int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
+// Validates a run, prepares the group buffers and stages the segment table of
+// the run on `st` (base_dev: optional device word added to every sample index).
+static int prepare_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, const uint64_t *base_dev,
+                       std::vector<SegDev> &segs, std::vector<int> &group_begin) {
     if (!c || !r) return fail(AMM_E_ARG, "amm_integrate: bad argument");
     if (r->graph_begin < 0 || r->graph_end > (int)c->slots.size() || r->graph_begin >= r->graph_end)
         return fail(AMM_E_ARG, "amm_integrate: bad graph range");
@@ -345,10 +370,8 @@ int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
     if (c->loops < 1 || c->loops > 4) return fail(AMM_E_ARG, "amm_integrate: unsupported loop order");
     if (c->loops == 1 && r->force_flag)
         return fail(AMM_E_ARG, "amm_integrate: double-double recompute is disabled at 1 loop (force_flag)");
-    hipStream_t st = (hipStream_t)stream;
+    if (r->blocks_per_cu < 0 || r->blocks_per_cu > 64) return fail(AMM_E_ARG, "amm_integrate: blocks_per_cu 0..64");
     HIPCHK(hipSetDevice(c->device));
-    int dev_cus = 256;
-    hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device);
     const int ne_ctx = 2 * c->loops - 1;
     if (c->ydd_ne < ne_ctx) {                 // DD results of up to one group of samples
         HIPCHK(hipFree(c->d_ydd));
@@ -357,13 +380,20 @@ int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
         HIPCHK(hipMalloc((void **)&c->d_ydd, (size_t)ne_ctx * MAX_GROUP_CHUNKS * CHUNK * sizeof(double)));
         c->ydd_ne = ne_ctx;
     }
+    // graph order inside groups: heaviest plan first (cost grouping) or natural
+    std::vector<int> order;
+    for (int g = r->graph_begin; g < r->graph_end; ++g) order.push_back(g);
+    if (c->order_by_cost)
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return c->slots[a].plan.flops_per_sample > c->slots[b].plan.flops_per_sample;
+        });
     // Segments: each graph's chunk range cut into pieces of at most one group;
     // groups: consecutive segments of distinct graphs, at most MAX_GROUP_CHUNKS.
     const uint64_t nchunks_total = (r->n_per_graph + CHUNK - 1) / CHUNK;
-    std::vector<SegDev> segs;
-    std::vector<int> group_begin;             // first segment of each group
+    segs.clear();
+    group_begin.clear();
     int gch = MAX_GROUP_CHUNKS, last_g = -1;
-    for (int g = r->graph_begin; g < r->graph_end; ++g) {
+    for (int g : order) {
         GraphSlot &s = c->slots[g];
         bool learned = r->sampler == 1 && s.d_ptheta != nullptr;
         for (uint64_t ch0 = 0; ch0 < nchunks_total; ch0 += MAX_GROUP_CHUNKS) {
@@ -383,6 +413,7 @@ int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
             S.A.ncls = s.ncls;
             for (int e = 0; e < MAXNE; ++e) S.A.cls_of[e] = e < s.ne ? s.cls_of[e] : 0;
             S.A.learned = learned ? 1 : 0;
+            S.A.base_dev = base_dev;
             if (r->force_flag) S.A.tau = -1.0;
             else if (r->accept_tau) S.A.tau = r->accept_tau[g - r->graph_begin];
             else S.A.tau = INFINITY;
@@ -412,18 +443,32 @@ int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
     std::memcpy(c->h_segs, segs.data(), segs.size() * sizeof(SegDev));
     HIPCHK(hipMemcpyAsync(c->d_segs, c->h_segs, segs.size() * sizeof(SegDev), hipMemcpyHostToDevice, st));
     HIPCHK(hipEventRecord(c->seg_ev, st));
+    return AMM_OK;
+}
+
+// Whether a group's FP64 pass runs as one persistent interpreter launch.
+static bool group_fused(const amm_ctx *c, const std::vector<SegDev> &segs, int k0, int k1) {
+    if (!c->use_fused) return false;
+    for (int k = k0; k < k1; ++k)
+        if (c->use_gen && gen_launch(c->loops, segs[k].g)) return false;
+    return true;
+}
+
+// Enqueues the kernels of every group of a prepared run on `st` (also used
+// under stream capture; then `prof` must be false).
+static void enqueue_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, const std::vector<SegDev> &segs,
+                        const std::vector<int> &group_begin, bool prof) {
+    int dev_cus = 256;
+    hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device);
     const SegDev *d_segs = (const SegDev *)c->d_segs;
-    if (!r->accumulate)
-        for (int g = r->graph_begin; g < r->graph_end; ++g)
-            hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, c->d_acc + (size_t)g * NSTAT_MAX, NSTAT_MAX);
-    const int grid_target = r->samples_per_thread > 0 ? r->samples_per_thread * dev_cus : 8 * dev_cus;
+    const int bpc = r->blocks_per_cu > 0 ? r->blocks_per_cu : (c->blocks_per_cu > 0 ? c->blocks_per_cu : 8);
+    const int grid_target = bpc * dev_cus;
     for (size_t q = 0; q + 1 < group_begin.size(); ++q) {
         const int k0 = group_begin[q], k1 = group_begin[q + 1];
         const int nch = segs[k1 - 1].gchunk + segs[k1 - 1].A.nchunks;
         amm_ctx::Ev ev, *evp = nullptr;
-        if (c->prof) {
-            HIPCHK(hipEventCreate(&ev.a)); HIPCHK(hipEventCreate(&ev.b));
-            HIPCHK(hipEventCreate(&ev.c)); HIPCHK(hipEventCreate(&ev.d));
+        if (prof) {
+            hipEventCreate(&ev.a); hipEventCreate(&ev.b); hipEventCreate(&ev.c); hipEventCreate(&ev.d);
             ev.samples = 0;
             ev.nseg = k1 - k0;
             for (int k = k0; k < k1; ++k) {
@@ -432,18 +477,29 @@ int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
                 ev.samples += (int64_t)(hi - lo);
             }
             evp = &ev;
-            HIPCHK(hipEventRecord(ev.a, st));
+            hipEventRecord(ev.a, st);
         }
-        for (int k = k0; k < k1; ++k) {
-            const int grid = std::min(segs[k].A.nchunks, grid_target);
+        if (group_fused(c, segs, k0, k1)) {
+            const int grid = std::min(nch, grid_target);
+            hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, c->d_work, 0);
             switch (c->loops) {
-                case 1: launch_seg_fp64<1>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
-                case 2: launch_seg_fp64<2>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
-                case 3: launch_seg_fp64<3>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
-                case 4: launch_seg_fp64<4>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
+                case 1: hipLaunchKernelGGL(k_integrate_fused<1>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, c->d_work, c->d_part, c->d_flag, c->d_nflag); break;
+                case 2: hipLaunchKernelGGL(k_integrate_fused<2>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, c->d_work, c->d_part, c->d_flag, c->d_nflag); break;
+                case 3: hipLaunchKernelGGL(k_integrate_fused<3>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, c->d_work, c->d_part, c->d_flag, c->d_nflag); break;
+                case 4: hipLaunchKernelGGL(k_integrate_fused<4>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, c->d_work, c->d_part, c->d_flag, c->d_nflag); break;
+            }
+        } else {
+            for (int k = k0; k < k1; ++k) {
+                const int grid = std::min(segs[k].A.nchunks, grid_target);
+                switch (c->loops) {
+                    case 1: launch_seg_fp64<1>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
+                    case 2: launch_seg_fp64<2>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
+                    case 3: launch_seg_fp64<3>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
+                    case 4: launch_seg_fp64<4>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
+                }
             }
         }
-        if (evp) HIPCHK(hipEventRecord(ev.b, st));
+        if (evp) hipEventRecord(ev.b, st);
         const int grid_red = std::min(nch, grid_target);
         switch (c->loops) {
             case 1: launch_group_tail<1>(c, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
@@ -452,11 +508,119 @@ int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
             case 4: launch_group_tail<4>(c, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
         }
         if (evp) {
-            HIPCHK(hipEventRecord(ev.d, st));
+            hipEventRecord(ev.d, st);
             c->evs.push_back(ev);
         }
-        HIPCHK(hipGetLastError());
     }
+}
+
+static void zero_acc(amm_ctx *c, const amm_run_params *r, hipStream_t st) {
+    if (!r->accumulate)
+        for (int g = r->graph_begin; g < r->graph_end; ++g)
+            hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, c->d_acc + (size_t)g * NSTAT_MAX, NSTAT_MAX);
+}
+
+int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<SegDev> segs;
+    std::vector<int> group_begin;
+    int rc = prepare_run(c, r, st, nullptr, segs, group_begin);
+    if (rc) return rc;
+    zero_acc(c, r, st);
+    enqueue_run(c, r, st, segs, group_begin, c->prof);
+    HIPCHK(hipGetLastError());
+    c->last_stream = st;
+    return AMM_OK;
+}
+
+int amm_integrate_batches(amm_ctx *c, const amm_run_params *r, uint64_t n_batches, void *stream) {
+    if (!c || !r || n_batches == 0) return fail(AMM_E_ARG, "amm_integrate_batches: bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(c->device));
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = c->cap_stream;
+    std::vector<SegDev> segs;
+    std::vector<int> group_begin;
+    int rc = prepare_run(c, r, st, c->d_base, segs, group_begin);
+    if (rc) return rc;
+    zero_acc(c, r, st);
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, st, c->d_base, (uint64_t)0);   // first batch at counter0
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&e0, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&e1, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(e0, st));
+    HIPCHK(hipStreamWaitEvent(cs, e0, 0));
+    // one batch: the groups' kernels, then the sample base advances by n_per_graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    enqueue_run(c, r, cs, segs, group_begin, false);
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, cs, c->d_base, r->n_per_graph);
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    if (ce != hipSuccess) {
+        hipEventDestroy(e0); hipEventDestroy(e1);
+        return fail(AMM_E_HIP, std::string("amm_integrate_batches: capture: ") + hipGetErrorString(ce));
+    }
+    ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    for (uint64_t b = 0; b < n_batches && ce == hipSuccess; ++b) ce = hipGraphLaunch(exec, cs);
+    if (ce == hipSuccess) ce = hipEventRecord(e1, cs);
+    if (ce == hipSuccess) ce = hipStreamWaitEvent(st, e1, 0);
+    hipStreamSynchronize(cs);
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (ce != hipSuccess) return fail(AMM_E_HIP, std::string("amm_integrate_batches: ") + hipGetErrorString(ce));
+    c->last_stream = st;
+    return AMM_OK;
+}
+
+int amm_autotune(amm_ctx *c, const amm_run_params *r, int *blocks_per_cu, int *order_by_cost, double *ms_best,
+                 void *stream) {
+    if (!c || !r || r->n_per_graph == 0) return fail(AMM_E_ARG, "amm_autotune: bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(c->device));
+    // the probe runs overwrite the accumulators of the graphs: keep a copy
+    const size_t nacc = c->slots.size() * NSTAT_MAX;
+    double *saved = nullptr;
+    HIPCHK(hipMalloc((void **)&saved, nacc * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(saved, c->d_acc, nacc * sizeof(double), hipMemcpyDeviceToDevice, st));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int bpcs[] = {1, 2, 4, 8, 16};
+    const int keep_order = c->order_by_cost, keep_prof = c->prof;
+    c->prof = false;
+    int best_b = 8, best_o = keep_order, rc = AMM_OK;
+    float best = 3.4e38f;
+    amm_run_params q = *r;
+    q.accumulate = 0;
+    for (int o = 0; o < 2 && rc == AMM_OK; ++o) {
+        c->order_by_cost = o;
+        for (int b : bpcs) {
+            q.blocks_per_cu = b;
+            if ((rc = amm_integrate(c, &q, st))) break;          // warm-up
+            hipEventRecord(e0, st);
+            if ((rc = amm_integrate(c, &q, st))) break;
+            hipEventRecord(e1, st);
+            hipEventSynchronize(e1);
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) { best = ms; best_b = b; best_o = o; }
+        }
+    }
+    c->prof = keep_prof;
+    hipMemcpyAsync(c->d_acc, saved, nacc * sizeof(double), hipMemcpyDeviceToDevice, st);
+    hipStreamSynchronize(st);
+    hipFree(saved);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) { c->order_by_cost = keep_order; return rc; }
+    c->blocks_per_cu = best_b;
+    c->order_by_cost = best_o;
+    if (blocks_per_cu) *blocks_per_cu = best_b;
+    if (order_by_cost) *order_by_cost = best_o;
+    if (ms_best) *ms_best = best;
     c->last_stream = st;
     return AMM_OK;
 }
@@ -482,7 +646,12 @@ int amm_profile(amm_ctx *c, int enable, double *ms_fp64, double *ms_dd, double *
 int amm_set_option(amm_ctx *c, int option, int value) {
     if (!c) return fail(AMM_E_ARG, "amm_set_option: ctx is NULL");
     if (option == AMM_OPT_GENERATED) c->use_gen = value != 0;
-    else return fail(AMM_E_ARG, "amm_set_option: unknown option");
+    else if (option == AMM_OPT_FUSED) c->use_fused = value != 0;
+    else if (option == AMM_OPT_ORDER_BY_COST) c->order_by_cost = value != 0;
+    else if (option == AMM_OPT_BLOCKS_PER_CU) {
+        if (value < 0 || value > 64) return fail(AMM_E_ARG, "amm_set_option: blocks per CU 0..64");
+        c->blocks_per_cu = value;
+    } else return fail(AMM_E_ARG, "amm_set_option: unknown option");
     return AMM_OK;
 }
 

@@ -43,7 +43,10 @@ struct RunArgs {
     int ncls;
     int cls_of[MAXNE];
     int learned;
+    const uint64_t *base_dev;       // optional device word added to every sample index (graph replays)
 };
+
+__device__ __forceinline__ uint64_t base_offset(const RunArgs &A) { return A.base_dev ? *A.base_dev : 0ull; }
 
 // One segment of a group: graph g's chunks [A.chunk0, A.chunk0 + A.nchunks)
 // of its sample range, stored at chunks [gchunk, gchunk + A.nchunks) of the
@@ -199,49 +202,105 @@ __device__ __forceinline__ void block_stats(const double (&st)[NST], int nst, do
     __syncthreads();
 }
 
+// One chunk (CHUNK consecutive samples, local chunk ch of the run A): FP64
+// pass, acceptance, flag compaction in sample order, per-chunk sums.  Called
+// by every thread of a BLOCK-thread block.
+template <int N, class Ev>
+__device__ __forceinline__ void process_chunk(const Ev &EV, const DensityDev &D, const RunArgs &A, int ch,
+                                              double *part_ch, uint32_t *flags_ch, int32_t *nflag_ch,
+                                              double (*shs)[3 * (2 * N - 1) + 2 * (2 * N - 1) + 4], int *shw,
+                                              double *vlds, float *rlds) {
+    constexpr int NE = 2 * N - 1;
+    constexpr int NST = 3 * NE + 2 * NE + 4;
+    constexpr int NW = BLOCK / 64;
+    const int nst = 3 * NE + 2 * A.ncls + 4;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double st[NST];
+    for (int s = 0; s < NST; ++s) st[s] = 0.0;
+    const uint64_t n_run = A.end - A.begin;
+    const uint64_t local0 = (uint64_t)(A.chunk0 + ch) * CHUNK;
+    const uint64_t base = base_offset(A) + A.begin + local0;
+    int fcount = 0;
+    for (int r = 0; r < RPC; ++r) {
+        const uint64_t off = (uint64_t)r * BLOCK + threadIdx.x;
+        int flag = 0, ood = 0, ddbad = 0;
+        double y[NE];
+        const bool live = local0 + off < n_run;
+        if (live) {
+            eval_sample<N>(EV, D, A, base + off, y, ood, flag, ddbad, vlds, rlds);
+            add_stats<N>(st, y, A);
+            st[nst - 4] += 1.0;
+            st[nst - 3] += flag;
+            st[nst - 1] += ood;
+        }
+        // compact the flagged offsets of this round in thread order
+        const bool f = live && flag;
+        const uint64_t m = __ballot(f);
+        if (lane == 0) shw[wv] = __popcll(m);
+        __syncthreads();
+        int pos = fcount + __popcll(m & ((1ull << lane) - 1ull));
+        for (int w = 0; w < wv; ++w) pos += shw[w];
+        if (f) flags_ch[pos] = (uint32_t)off | (ddbad ? FLAG_DDFAIL : 0u);
+        for (int w = 0; w < NW; ++w) fcount += shw[w];
+        __syncthreads();
+    }
+    block_stats<NST, BLOCK>(st, nst, shs, part_ch, false);
+    if (threadIdx.x == 0) *nflag_ch = fcount;
+}
+
+// FP64 pass of one segment: blocks stride over its chunks.
 template <int N, class Ev>
 __global__ void __launch_bounds__(BLOCK) k_integrate(Ev EV, DensityDev D, RunArgs A, double *part, uint32_t *flags,
                                                      int32_t *nflag) {
     constexpr int NE = 2 * N - 1;
     constexpr int NST = 3 * NE + 2 * NE + 4;
-    constexpr int NW = BLOCK / 64;
-    __shared__ double shs[NW][NST];
-    __shared__ int shw[NW];
+    __shared__ double shs[BLOCK / 64][NST];
+    __shared__ int shw[BLOCK / 64];
     __shared__ double vlds[(Ev::kLds ? Dims<N>::NV : 1) * BLOCK];
     __shared__ float rlds[(Ev::kLds ? Dims<N>::NV : 1) * BLOCK];
-    const int nst = 3 * NE + 2 * A.ncls + 4;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int ch = blockIdx.x; ch < A.nchunks; ch += gridDim.x) {
-        double st[NST];
-        for (int s = 0; s < NST; ++s) st[s] = 0.0;
-        uint64_t base = A.begin + (uint64_t)(A.chunk0 + ch) * CHUNK;
-        int fcount = 0;
-        for (int r = 0; r < RPC; ++r) {
-            uint64_t idx = base + (uint64_t)r * BLOCK + threadIdx.x;
-            int flag = 0, ood = 0, ddbad = 0;
-            double y[NE];
-            bool live = idx < A.end;
-            if (live) {
-                eval_sample<N>(EV, D, A, idx, y, ood, flag, ddbad, vlds, rlds);
-                add_stats<N>(st, y, A);
-                st[nst - 4] += 1.0;
-                st[nst - 3] += flag;
-                st[nst - 1] += ood;
-            }
-            // compact the flagged offsets of this round in thread order
-            const bool f = live && flag;
-            const uint64_t m = __ballot(f);
-            if (lane == 0) shw[wv] = __popcll(m);
-            __syncthreads();
-            int pos = fcount + __popcll(m & ((1ull << lane) - 1ull));
-            for (int w = 0; w < wv; ++w) pos += shw[w];
-            if (f) flags[(size_t)ch * CHUNK + pos] = (uint32_t)(r * BLOCK + threadIdx.x) | (ddbad ? FLAG_DDFAIL : 0u);
-            for (int w = 0; w < NW; ++w) fcount += shw[w];
-            __syncthreads();
-        }
-        block_stats<NST, BLOCK>(st, nst, shs, part + (size_t)ch * NSTAT_MAX, false);
-        if (threadIdx.x == 0) nflag[ch] = fcount;
+    for (int ch = blockIdx.x; ch < A.nchunks; ch += gridDim.x)
+        process_chunk<N>(EV, D, A, ch, part + (size_t)ch * NSTAT_MAX, flags + (size_t)ch * CHUNK, nflag + ch, shs,
+                         shw, vlds, rlds);
+}
+
+// FP64 pass of a whole group with the table interpreter: a persistent grid
+// whose blocks take the group's chunks in order from a work counter (segments
+// are ordered heaviest graph first when grouping by cost).  Every block exits
+// once the counter passes the group's chunk count.
+template <int N>
+__global__ void __launch_bounds__(BLOCK) k_integrate_fused(const SegDev *segs, int nseg, int nch, int *work,
+                                                           double *part, uint32_t *flags, int32_t *nflag) {
+    constexpr int NE = 2 * N - 1;
+    constexpr int NST = 3 * NE + 2 * NE + 4;
+    __shared__ double shs[BLOCK / 64][NST];
+    __shared__ int shw[BLOCK / 64];
+    __shared__ double vlds[Dims<N>::NV * BLOCK];
+    __shared__ float rlds[Dims<N>::NV * BLOCK];
+    __shared__ int item;
+    for (;;) {
+        if (threadIdx.x == 0) item = atomicAdd(work, 1);
+        __syncthreads();
+        const int gc = item;
+        __syncthreads();
+        if (gc >= nch) break;                 // uniform over the block
+        const SegDev &S = segs[seg_of_chunk(segs, nseg, gc)];
+        const InterpEval EV{S.P};
+        process_chunk<N>(EV, S.D, S.A, gc - S.gchunk, part + (size_t)gc * NSTAT_MAX, flags + (size_t)gc * CHUNK,
+                         nflag + gc, shs, shw, vlds, rlds);
     }
+}
+
+static __global__ void k_set_int(int *p, int v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+static __global__ void k_set_u64(uint64_t *p, uint64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// Advances the device-resident sample base after a replay of a captured batch.
+static __global__ void k_advance(uint64_t *base, uint64_t step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *base += step;
 }
 
 // Exclusive scan of the per-chunk flag counts (one block of 1024 threads;
@@ -304,7 +363,8 @@ __global__ void __launch_bounds__(DD_BLOCK) k_dd_points(const SegDev *segs, int 
         bool fail = (w & FLAG_DDFAIL) != 0u;
         double y[NE];
         if (!fail) {
-            uint64_t idx = S.A.begin + (uint64_t)(S.A.chunk0 + (lo - S.gchunk)) * CHUNK + (w & ~FLAG_DDFAIL);
+            uint64_t idx = base_offset(S.A) + S.A.begin + (uint64_t)(S.A.chunk0 + (lo - S.gchunk)) * CHUNK +
+                           (w & ~FLAG_DDFAIL);
             double u[2 * M], z[M];
             int path[M];
             uniforms(S.A.seed, S.A.uid, idx, S.D.ptheta ? 2 * M : 2 * M - 1, u);

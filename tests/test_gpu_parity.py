@@ -215,9 +215,9 @@ def test_two_loop_value_full_size(amm):
 
 def test_determinism_across_grid_sizes(amm):
     _ctx_for(amm, 2)
-    amm.integrate(seed=3, n_per_graph=700_001, samples_per_thread=1)
+    amm.integrate(seed=3, n_per_graph=700_001, blocks_per_cu=1)
     a = [amm.read(g, e) for g in range(2) for e in range(3)]
-    amm.integrate(seed=3, n_per_graph=700_001, samples_per_thread=7)
+    amm.integrate(seed=3, n_per_graph=700_001, blocks_per_cu=7)
     b = [amm.read(g, e) for g in range(2) for e in range(3)]
     assert a == b
 
