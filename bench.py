@@ -129,6 +129,8 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-learned', action='store_true', help='skip the learned-sampler sigma^2*time measurement')
     ap.add_argument('--no-other-orders', action='store_true', help='skip the 1-, 2- and 4-loop measurements')
+    ap.add_argument('--copy-probe', type=int, default=0, metavar='BYTES',
+                    help='only copy BYTES between two device buffers (calibrates HBM byte counters) and exit')
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) != 1:
         print('bench.py: this build runs on one GPU only; multi-GPU runs are not part of it '
@@ -136,6 +138,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        x = torch.empty(args.copy_probe // 8, dtype=torch.float64, device='cuda').fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
     from paper_1909_08015_amd import Context
 
     ctx = Context(0)

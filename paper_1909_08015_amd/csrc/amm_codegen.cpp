@@ -10,6 +10,7 @@
 // evaluated once per point and shared by the terms that contain them.
 //
 // Usage: amm_codegen <loops> <out.hip>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -76,11 +77,18 @@ class GraphGen {
   public:
     GraphGen(const PlanHost &P, int gi) : P(P), gi(gi), N(P.n) {}
 
+    // One non-inlined device function per forest term (its level values, with
+    // the few sub-levels it shares with other terms recomputed, live only
+    // inside it), called in term order by Fun::eval.  Small functions keep the
+    // register allocation per term and the compile time near linear in size.
     std::string run() {
-        E.os << "struct Fun {\ntemplate <typename T>\nstatic __device__ __forceinline__ void eval(const double *z, T *I, T *absI) {\n";
-        for (int j = 0; j < P.M; ++j) E.os << "  const double z" << j << " = z[" << j << "];\n";
-        for (int e = 0; e < P.ninsert; ++e) E.os << "  I[" << e << "] = T(0.0); absI[" << e << "] = T(0.0);\n";
+        std::ostringstream funcs, body;
+        int t = 0;
         for (const TermDesc &td : P.terms) {
+            E.os.str("");
+            E.os.clear();
+            memo.clear();
+            for (int j = 0; j < P.M; ++j) E.os << "  const double z" << j << " = z[" << j << "];\n";
             std::vector<int> ops(P.ops.begin() + td.op_begin, P.ops.begin() + td.op_end);
             SubVal root = subtree(ops, (int)ops.size());
             // sum_c vec[c] Gamma(n-c) / V^{n-c}
@@ -97,9 +105,17 @@ class GraphGen {
             }
             E.os << "    I[" << td.e << "] += " << (td.sign > 0 ? "" : "-") << val << ";\n";
             E.os << "    absI[" << td.e << "] += absd(" << val << ");\n  }\n";
+            funcs << "template <typename T>\nstatic __device__ __attribute__((noinline)) void term" << t
+                  << "(const double *z, T *I, T *absI) {\n" << E.os.str() << "}\n";
+            body << "  term" << t << "<T>(z, I, absI);\n";
+            ++t;
         }
-        E.os << "}\n};\n";
-        return E.os.str();
+        std::ostringstream out;
+        out << funcs.str();
+        out << "struct Fun {\ntemplate <typename T>\nstatic __device__ __forceinline__ void eval(const double *z, T *I, T *absI) {\n";
+        for (int e = 0; e < P.ninsert; ++e) out << "  I[" << e << "] = T(0.0); absI[" << e << "] = T(0.0);\n";
+        out << body.str() << "}\n};\n";
+        return out.str();
     }
 
   private:
@@ -235,6 +251,13 @@ class GraphGen {
                 o << ");\n";
             }
         }
+        // values of the used variables and their largest relative error (T = ea)
+        o << "    double rmx = 0.0;\n";
+        for (size_t id = 0; id < used.size(); ++id)
+            if (used[id])
+                o << "    const double x" << id << " = to_double(v" << id << "); rmx = fmax(rmx, relerr(v" << id
+                  << "));\n";
+        o << "    const double rm1 = rmx + 1.0;\n";
         // base prefactor
         char pb[64];
         std::snprintf(pb, sizeof pb, "%a", d.pref);
@@ -266,16 +289,20 @@ class GraphGen {
                 o << "      {\n      T own[" << N << "];\n      T fac = base;\n";
                 for (int c = 0; c < N; ++c) {
                     auto r = P.ranges[d.mono_range + (var * d.nout + oo) * (P.n + 1) + c];
-                    o << "      {\n        T acc = T(0.0);\n";
+                    // FP64 value and first-order error bound of the range (as the
+                    // interpreter's ea path): p = coef x_1 ... x_nv has relative
+                    // error at most nv (rmax + 1) + 1; each accumulation adds |av|
+                    o << "      {\n        double av = 0.0, ae = 0.0;\n";
                     for (int m = r.first; m < r.second; ++m) {
                         const Mono &mo = P.monos[m];
-                        std::string t = mo.nv ? "v" + std::to_string(mo.v[0]) : "T(1.0)";
-                        for (int i = 1; i < mo.nv; ++i) t = t + " * v" + std::to_string(mo.v[i]);
                         char cb[64];
                         std::snprintf(cb, sizeof cb, "%a", mo.coef);
-                        o << "        acc = mul_add(T(" << cb << "), " << t << ", acc);\n";
+                        std::string pe = cb;
+                        for (int i = 0; i < mo.nv; ++i) pe = pe + " * x" + std::to_string(mo.v[i]);
+                        o << "        { const double p = " << pe << "; av = av + p; ae = fma(fabs(p), fma("
+                          << (int)mo.nv << ".0, rm1, 1.0), ae) + fabs(av); }\n";
                     }
-                    o << "        own[" << c << "] = acc * fac;\n";
+                    o << "        own[" << c << "] = ea(av, ae) * fac;\n";
                     if (c + 1 < N) o << "        fac = fac * T(-0.5);\n";
                     o << "      }\n";
                 }

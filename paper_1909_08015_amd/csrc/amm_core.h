@@ -5,6 +5,7 @@
 // Paper references: sampling and density Sec. III.A (eq. pdf, pdf_final),
 // g stored as x 2^j Sec. IV.A, forest formula Sec. II, estimator Sec. III.B.
 #pragma once
+#include <type_traits>
 #include <math.h>
 #include <stdint.h>
 
@@ -82,31 +83,56 @@ AMM_HDI dd mul_add(dd a, dd b, dd c) { return a * b + c; }
 // propagation; the rounding error of v is bounded by ~k u a for an
 // operation-chain depth k.
 // ---------------------------------------------------------------------------
+// FP64 value with a first-order running error bound (Wilkinson's running
+// error analysis): |v - exact| <= u a, u = 2^-53.  Every operation adds the
+// rounding of its own result, |result|, to the propagated errors of its
+// operands; constants are counted as rounded once.
 struct ea {
     double v, a;
     AMM_HDI ea() : v(0), a(0) {}
     AMM_HDI ea(double x) : v(x), a(fabs(x)) {}
     AMM_HDI ea(double x, double m) : v(x), a(m) {}
 };
-AMM_HDI ea operator+(ea x, ea y) { return ea(x.v + y.v, x.a + y.a); }
+AMM_HDI ea operator+(ea x, ea y) {
+    double z = x.v + y.v;
+    return ea(z, (x.a + y.a) + fabs(z));
+}
 AMM_HDI ea operator-(ea x) { return ea(-x.v, x.a); }
-AMM_HDI ea operator-(ea x, ea y) { return ea(x.v - y.v, x.a + y.a); }
-AMM_HDI ea operator*(ea x, ea y) { return ea(x.v * y.v, x.a * y.a); }
+AMM_HDI ea operator-(ea x, ea y) {
+    double z = x.v - y.v;
+    return ea(z, (x.a + y.a) + fabs(z));
+}
+AMM_HDI ea operator*(ea x, ea y) {
+    double z = x.v * y.v;
+    return ea(z, fma(x.a, fabs(y.v), fma(y.a, fabs(x.v), fabs(z))));
+}
 AMM_HDI ea operator/(ea x, ea y) {
     double q = x.v / y.v, ay = fabs(y.v);
-    return ea(q, (x.a + fabs(q) * y.a) / ay);
+    return ea(q, fma(fabs(q), y.a, x.a) / ay + fabs(q));
 }
 AMM_HDI ea &operator+=(ea &x, ea y) { x = x + y; return x; }
 AMM_HDI ea &operator-=(ea &x, ea y) { x = x - y; return x; }
 AMM_HDI ea &operator*=(ea &x, ea y) { x = x * y; return x; }
 AMM_HDI double to_double(ea x) { return x.v; }
 AMM_HDI ea absd(ea x) { return ea(fabs(x.v), x.a); }
-AMM_HDI ea mul_add(ea x, ea y, ea z) { return ea(fma(x.v, y.v, z.v), fma(x.a, y.a, z.a)); }
+AMM_HDI ea mul_add(ea x, ea y, ea z) {
+    double w = fma(x.v, y.v, z.v);
+    return ea(w, fma(x.a, fabs(y.v), fma(y.a, fabs(x.v), z.a + fabs(w))));
+}
 AMM_HDI double mag(ea x) { return x.a; }
-// Drop the accumulated magnitude (treat as exact): used for the outputs of
-// the backward-stable LDL^T factorisation and solves, whose relative errors
-// stay at a few u; cancellation is tracked from the dot products onwards.
-AMM_HDI ea strip(ea x) { return ea(x.v); }
+// Kept as an identity: every operation's error is propagated.
+AMM_HDI ea strip(ea x) { return x; }
+// Relative error bound a / |v| (units of u); infinite for a zero value with a
+// nonzero error.  On the device the reciprocal is the hardware approximation,
+// enlarged by 2^-16 so that the result stays an upper bound.
+AMM_HDI double relerr(ea x) {
+    if (!(x.a > 0.0)) return 0.0;
+#if defined(__HIP_DEVICE_COMPILE__)
+    return x.a * __builtin_amdgcn_rcp(fabs(x.v)) * (1.0 + 0x1p-16);
+#else
+    return x.a / fabs(x.v);
+#endif
+}
 AMM_HDI double strip(double x) { return x; }
 AMM_HDI dd strip(dd x) { return x; }
 AMM_HDI double mag(double x) { return fabs(x); }
@@ -361,6 +387,46 @@ template <int N> struct Dims {
     static constexpr int DEPTH = 2 * N + 1;
 };
 
+// Sum of the monomials coef * prod vars of one range.  Generic arithmetic,
+// or, for T = ea, the value in FP64 with a first-order error bound: with
+// rmax the largest relative error (units of u) of the level's variables, the
+// product p = coef x_1 ... x_nv has relative error at most
+// nv (rmax + 1) + 1 (its variables, its nv roundings, the rounded
+// coefficient), and each accumulation adds |partial sum|.
+template <typename T, typename Vars>
+AMM_HDI T poly_range(const PlanDev &P, int2 r, const Vars &vars, double rmax) {
+    if constexpr (std::is_same<T, ea>::value) {
+        double av = 0.0, ae = 0.0;
+        const double r1 = rmax + 1.0;
+        for (int m = r.x; m < r.y; ++m) {
+            const Mono &mo = P.monos[m];
+            double p = mo.coef;
+            for (int i = 0; i < mo.nv; ++i) p = p * vars.val(mo.v[i]);
+            av = av + p;
+            ae = fma(fabs(p), fma((double)mo.nv, r1, 1.0), ae) + fabs(av);
+        }
+        return ea(av, ae);
+    } else {
+        T acc = T(0.0);
+        for (int m = r.x; m < r.y; ++m) {
+            const Mono &mo = P.monos[m];
+            T t = mo.nv ? vars.get(mo.v[0]) : T(1.0);
+            for (int i = 1; i < mo.nv; ++i) t = t * vars.get(mo.v[i]);
+            acc = mul_add(T(mo.coef), t, acc);
+        }
+        return acc;
+    }
+}
+
+// Largest relative error bound of a level's variables 0..n-1 (ea only).
+template <typename T, typename Vars>
+AMM_HDI double level_rmax(const Vars &vars, int n) {
+    double m = 0.0;
+    if constexpr (std::is_same<T, ea>::value)
+        for (int i = 0; i < n; ++i) m = fmax(m, vars.rel(i));
+    return m;
+}
+
 // Truncated convolution of two c-vectors of length N.
 template <typename T, int N>
 AMM_HDI void conv_into(const T *a, const T *b, T *out) {
@@ -381,6 +447,8 @@ template <typename T, int NV> struct VarsPriv {
     AMM_HDI void begin() {}
     AMM_HDI void set(int i, const T &x) { v[i] = x; }
     AMM_HDI T get(int i) const { return v[i]; }
+    AMM_HDI double val(int i) const { return to_double(v[i]); }
+    AMM_HDI double rel(int i) const { return relerr(v[i]); }
 };
 struct VarsLdsD {
     double *base;
@@ -397,12 +465,14 @@ struct VarsLdsEa {
     AMM_HDI void set(int i, const ea &x) {
         base[i * stride] = x.v;
         double ax = fabs(x.v);
-        rbase[i * stride] = ax > 0.0 ? (float)(x.a / ax) : (x.a > 0.0 ? INFINITY : 1.0f);
+        rbase[i * stride] = x.a > 0.0 ? (float)(x.a / ax) * (1.0f + 0x1p-20f) : 0.0f;
     }
     AMM_HDI ea get(int i) const {
         double v = base[i * stride];
         return ea(v, fabs(v) * (double)rbase[i * stride]);
     }
+    AMM_HDI double val(int i) const { return base[i * stride]; }
+    AMM_HDI double rel(int i) const { return (double)rbase[i * stride]; }
 };
 
 // Evaluate one level: c-vectors per output (pushed on the value stack) given
@@ -534,6 +604,7 @@ AMM_HDI void eval_level(const PlanDev &P, const LevelDesc &d, const double *z, T
             vars.set(XN + K + k - 1, T(k <= d.ext_node ? -0.5 : 0.5) - s);
         }
     }
+    const double rmax = level_rmax<T>(vars, d.op == OP_A ? XN + 2 * K : XN + K);
     // prefactor per c: pref (-1/2)^c / U^2 (* z_e for the merged line)
     T base = T(d.pref) / (U * U);
     if (d.has_X) {
@@ -583,13 +654,7 @@ AMM_HDI void eval_level(const PlanDev &P, const LevelDesc &d, const double *z, T
 #pragma unroll
             for (int c = 0; c < N; ++c) {
                 int2 r = P.ranges[d.mono_range + (var * d.nout + o) * (P.n + 1) + c];
-                T acc = T(0.0);
-                for (int m = r.x; m < r.y; ++m) {
-                    const Mono &mo = P.monos[m];
-                    T t = mo.nv ? vars.get(mo.v[0]) : T(1.0);
-                    for (int i = 1; i < mo.nv; ++i) t = t * vars.get(mo.v[i]);
-                    acc = mul_add(T(mo.coef), t, acc);
-                }
+                T acc = poly_range<T>(P, r, vars, rmax);
                 own[c] = acc * fac;
                 fac = fac * T(-0.5);
             }

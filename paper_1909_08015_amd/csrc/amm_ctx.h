@@ -25,7 +25,7 @@ constexpr int CHUNK = BLOCK * RPC;            // samples per chunk (the unit of 
 constexpr int MAX_GROUP_CHUNKS = 32768;       // chunks per group (33.5M samples): one DD pass each
 constexpr int DD_BLOCK = 64;                  // one wave per block in the double-double recompute
 constexpr uint32_t FLAG_DDFAIL = 0x80000000u; // flag word: the DD bound cannot pass either
-constexpr double KAPPA = 64.0;                // round-off bound multiplier (reading R11)
+constexpr double KAPPA = 2.0;                 // safety factor on the first-order running error bound
 constexpr int MAXNE = 2 * MAXN - 1;
 constexpr int NSTAT_MAX = 3 * MAXNE + 2 * MAXNE + 4;
 
