@@ -56,6 +56,21 @@ def cpu_baseline(seconds_target=15.0):
             "seconds": dt}
 
 
+def counters_record():
+    """HBM bytes and executed FP64 flops per sample of the 3-loop FP64 pass,
+    from the committed rocprofv3 counter runs, if they were taken on this very
+    library build (same sha256); else None."""
+    import hashlib
+    rec_path = os.path.join(ROOT, 'profiles', 'k_integrate_3loop_counters.json')
+    lib_path = os.path.join(ROOT, 'paper_1909_08015_amd', 'libamm.so')
+    try:
+        rec = json.load(open(rec_path))
+        sha = hashlib.sha256(open(lib_path, 'rb').read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return rec if rec.get('libamm_sha256') == sha else None
+
+
 def _timed(torch, fn):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -181,6 +196,7 @@ def main():
     total_flops = sum(flops) * args.steps * B
     achieved = total_flops / (prof['ms_fp64'] * 1e-3) if prof['ms_fp64'] > 0 else 0.0
     est = ctx.read(-1, -1, None)
+    rec = counters_record()
     out = {
         "metric": "integrand evals/s + FP64 % of peak; sigma^2*time learned vs plain sampler, 5-loop",
         "value": value,
@@ -196,10 +212,16 @@ def main():
         "vertex_graph_evals_per_s": value * 5,
         "fp64_frac_of_peak": achieved / PEAK_FP64_VALU,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
+                     "traffic": (None if rec is None else
+                                 (rec['fetch_bytes_per_sample'] + rec['write_bytes_per_sample']) * B),
                      "kernel": "k_integrate<3>", "kernel_ms": prof['ms_fp64'],
                      "kernel_launches": prof['launches'],
                      "flops_per_sample": {str(g): flops[g] for g in range(G)}},
+        "traffic_unit": "HBM bytes per FP64-pass launch (one graph, batch_per_graph samples), calibrated "
+                        "FETCH_SIZE + WRITE_SIZE scaled from the committed counter runs of this library build",
+        "executed_fp64_tflops": (None if rec is None else
+                                 rec['executed_fp64_flops_per_sample'] * samples / (prof['ms_fp64'] * 1e-3) / 1e12),
         "phase_ms": {"fp64": prof['ms_fp64'], "dd": prof['ms_dd'], "reduce": prof['ms_reduce']},
         "estimate_3loop_so_far": {"mean": est['mean'], "sigma": est['sigma'], "n": est['n'],
                                   "n_flag": est['n_flag'], "n_dd_fail": est['n_dd_fail'], "n_ood": est['n_ood']},

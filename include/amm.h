@@ -90,7 +90,7 @@ typedef struct {
     int n_terms_expanded;   /* with (L-U) split in two, Sec. II counting     */
     int n_level_evals;      /* level evaluations per sample                  */
     int64_t n_monomials;    /* numerator monomials evaluated per sample      */
-    double flops_per_sample;/* algorithmic FP64 flops per sample, FMA = 2    */
+    double flops_per_sample;/* algorithmic FP64 flops per sample (values only: a monomial of nv variables counts nv + 1; FMA = 2), excluding the sampler and the error bound */
 } amm_plan_info;
 
 /* Create a context on HIP device `device`. */

@@ -784,7 +784,7 @@ void build_plan(const SEGraph &g, PlanHost &P) {
                             auto r = P.ranges[d.mono_range + (var * d.nout + o) * (n + 1) + c];
                             for (int m = r.first; m < r.second; ++m) {
                                 P.n_monos_per_sample += 1;
-                                P.flops_per_sample += 2.0 * P.monos[m].nv;   // nv-1 mul + 1 fma
+                                P.flops_per_sample += P.monos[m].nv + 1.0;   // nv multiplies + 1 add
                             }
                         }
                 int Lq = d.L;

