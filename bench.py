@@ -124,11 +124,27 @@ def other_loop_orders(ctx, args):
         prof = ctx.profile(False)
         est = ctx.read(-1, -1, None)
         achieved = flops * per_graph / (prof['ms_fp64'] * 1e-3)
+        learned = None
+        if n == 4:
+            # learned sampler on the 4-loop set: pilot (seed 1) -> GPU training ->
+            # sigma^2 * time of the learned mixture against the plain density
+            t_pilot = _timed(torch, lambda: ctx.pilot(1, 50_000))
+            t_train = _timed(torch, lambda: ctx.mlp_train(200, lr=1e-2, init_seed=0))
+            res = {}
+            for name, smp in (('plain', 0), ('learned', 1)):
+                t = _timed(torch, lambda: ctx.integrate(seed=2, n_per_graph=per_graph, sampler=smp, accept_tau=tau))
+                res[name] = (sum(ctx.read(g, -1)['sigma'] ** 2 for g in range(G)), t, ctx.read(-1, -1, None))
+            (vp, tp, ep), (vl, tl, el) = res['plain'], res['learned']
+            learned = {"sigma2_time_ratio_learned_over_plain": (vl * tl) / (vp * tp), "var_plain": vp,
+                       "var_learned": vl, "s_plain": tp, "s_learned": tl, "mean_plain": ep['mean'],
+                       "sigma_plain": ep['sigma'], "mean_learned": el['mean'], "sigma_learned": el['sigma'],
+                       "pilot_samples_per_graph": 50_000, "pilot_s": t_pilot, "train_epochs": 200, "train_s": t_train,
+                       "samples_per_graph": per_graph, "seed": 2}
         out[str(n)] = {"graphs": G, "samples_per_graph": per_graph, "samples_per_s": G * per_graph / dt,
                        "fp64_pass_ms": prof['ms_fp64'], "dd_ms": prof['ms_dd'],
                        "fp64_tflops": achieved / 1e12, "fp64_frac_of_peak": achieved / PEAK_FP64_VALU,
                        "flag_rate": est['n_flag'] / max(est['n'], 1), "n_dd_fail": est['n_dd_fail'],
-                       "tables_build_s": t_build, "autotune": tune,
+                       "tables_build_s": t_build, "autotune": tune, "learned_vs_plain": learned,
                        "evaluator": "generated" if n < 4 else "interpreter, fused persistent launch"}
     return out
 

@@ -421,10 +421,8 @@ AMM_HDI T poly_range(const PlanDev &P, int2 r, const Vars &vars, double rmax) {
 // Largest relative error bound of a level's variables 0..n-1 (ea only).
 template <typename T, typename Vars>
 AMM_HDI double level_rmax(const Vars &vars, int n) {
-    double m = 0.0;
-    if constexpr (std::is_same<T, ea>::value)
-        for (int i = 0; i < n; ++i) m = fmax(m, vars.rel(i));
-    return m;
+    if constexpr (std::is_same<T, ea>::value) return vars.max_rel(n);
+    else return 0.0;
 }
 
 // Truncated convolution of two c-vectors of length N.
@@ -448,7 +446,11 @@ template <typename T, int NV> struct VarsPriv {
     AMM_HDI void set(int i, const T &x) { v[i] = x; }
     AMM_HDI T get(int i) const { return v[i]; }
     AMM_HDI double val(int i) const { return to_double(v[i]); }
-    AMM_HDI double rel(int i) const { return relerr(v[i]); }
+    AMM_HDI double max_rel(int n) const {
+        double m = 0.0;
+        for (int i = 0; i < n; ++i) m = fmax(m, relerr(v[i]));
+        return m;
+    }
 };
 struct VarsLdsD {
     double *base;
@@ -458,21 +460,20 @@ struct VarsLdsD {
     AMM_HDI double get(int i) const { return base[i * stride]; }
 };
 struct VarsLdsEa {
-    double *base;      // values
-    float *rbase;      // magnitude / |value| per variable
+    double *base;      // values, one LDS column per thread
     int stride;
-    AMM_HDI void begin() {}
+    double rmax;       // largest relative error bound of the variables set since begin()
+    AMM_HDI void begin() { rmax = 0.0; }
     AMM_HDI void set(int i, const ea &x) {
         base[i * stride] = x.v;
-        double ax = fabs(x.v);
-        rbase[i * stride] = x.a > 0.0 ? (float)(x.a / ax) * (1.0f + 0x1p-20f) : 0.0f;
+        rmax = fmax(rmax, relerr(x));
     }
     AMM_HDI ea get(int i) const {
         double v = base[i * stride];
-        return ea(v, fabs(v) * (double)rbase[i * stride]);
+        return ea(v, fabs(v) * rmax);
     }
     AMM_HDI double val(int i) const { return base[i * stride]; }
-    AMM_HDI double rel(int i) const { return (double)rbase[i * stride]; }
+    AMM_HDI double max_rel(int) const { return rmax; }
 };
 
 // Evaluate one level: c-vectors per output (pushed on the value stack) given

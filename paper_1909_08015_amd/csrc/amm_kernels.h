@@ -81,8 +81,7 @@ __global__ void __launch_bounds__(BLOCK) k_eval(Ev EV, const double *z, uint64_t
     T v[NE], a[NE];
     if constexpr (std::is_same<T, ea>::value && Ev::kLds) {
         __shared__ double vlds[Dims<N>::NV * BLOCK];
-        __shared__ float rlds[Dims<N>::NV * BLOCK];
-        VarsLdsEa vars{vlds + threadIdx.x, rlds + threadIdx.x, BLOCK};
+        VarsLdsEa vars{vlds + threadIdx.x, BLOCK, 0.0};
         EV.template eval<T, N>(zz, v, a, vars);
     } else {
         VarsPriv<T, Ev::kLds ? Dims<N>::NV : 1> vars;
@@ -127,7 +126,7 @@ __device__ __forceinline__ void add_stats(double (&st)[3 * (2 * N - 1) + 2 * (2 
 // bound (KAPPA 2^-104 a / g) cannot pass either, so the recompute is skipped.
 template <int N, class Ev>
 __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, const RunArgs &A, uint64_t idx,
-                                            double *y, int &ood, int &flag, int &ddbad, double *vlds, float *rlds) {
+                                            double *y, int &ood, int &flag, int &ddbad, double *vlds) {
     constexpr int M = 3 * N - 1, NE = 2 * N - 1;
     double u[2 * M], z[M];
     int path[M];
@@ -156,7 +155,7 @@ __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, c
     } else {
         ea I[NE], aI[NE];
         if constexpr (Ev::kLds) {
-            VarsLdsEa vars{vlds + threadIdx.x, rlds + threadIdx.x, BLOCK};
+            VarsLdsEa vars{vlds + threadIdx.x, BLOCK, 0.0};
             EV.template eval<ea, N>(z, I, aI, vars);
         } else {
             VarsPriv<ea, 1> vars;
@@ -211,7 +210,7 @@ template <int N, class Ev>
 __device__ __forceinline__ void process_chunk(const Ev &EV, const DensityDev &D, const RunArgs &A, int ch,
                                               double *part_ch, uint32_t *flags_ch, int32_t *nflag_ch,
                                               double (*shs)[3 * (2 * N - 1) + 2 * (2 * N - 1) + 4], int *shw,
-                                              double *vlds, float *rlds) {
+                                              double *vlds) {
     constexpr int NE = 2 * N - 1;
     constexpr int NST = 3 * NE + 2 * NE + 4;
     constexpr int NW = BLOCK / 64;
@@ -229,7 +228,7 @@ __device__ __forceinline__ void process_chunk(const Ev &EV, const DensityDev &D,
         double y[NE];
         const bool live = local0 + off < n_run;
         if (live) {
-            eval_sample<N>(EV, D, A, base + off, y, ood, flag, ddbad, vlds, rlds);
+            eval_sample<N>(EV, D, A, base + off, y, ood, flag, ddbad, vlds);
             add_stats<N>(st, y, A);
             st[nst - 4] += 1.0;
             st[nst - 3] += flag;
@@ -259,10 +258,9 @@ __global__ void __launch_bounds__(BLOCK) k_integrate(Ev EV, DensityDev D, RunArg
     __shared__ double shs[BLOCK / 64][NST];
     __shared__ int shw[BLOCK / 64];
     __shared__ double vlds[(Ev::kLds ? Dims<N>::NV : 1) * BLOCK];
-    __shared__ float rlds[(Ev::kLds ? Dims<N>::NV : 1) * BLOCK];
     for (int ch = blockIdx.x; ch < A.nchunks; ch += gridDim.x)
         process_chunk<N>(EV, D, A, ch, part + (size_t)ch * NSTAT_MAX, flags + (size_t)ch * CHUNK, nflag + ch, shs,
-                         shw, vlds, rlds);
+                         shw, vlds);
 }
 
 // FP64 pass of a whole group with the table interpreter: a persistent grid
@@ -277,7 +275,6 @@ __global__ void __launch_bounds__(BLOCK) k_integrate_fused(const SegDev *segs, i
     __shared__ double shs[BLOCK / 64][NST];
     __shared__ int shw[BLOCK / 64];
     __shared__ double vlds[Dims<N>::NV * BLOCK];
-    __shared__ float rlds[Dims<N>::NV * BLOCK];
     __shared__ int item;
     for (;;) {
         if (threadIdx.x == 0) item = atomicAdd(work, 1);
@@ -288,7 +285,7 @@ __global__ void __launch_bounds__(BLOCK) k_integrate_fused(const SegDev *segs, i
         const SegDev &S = segs[seg_of_chunk(segs, nseg, gc)];
         const InterpEval EV{S.P};
         process_chunk<N>(EV, S.D, S.A, gc - S.gchunk, part + (size_t)gc * NSTAT_MAX, flags + (size_t)gc * CHUNK,
-                         nflag + gc, shs, shw, vlds, rlds);
+                         nflag + gc, shs, shw, vlds);
     }
 }
 

@@ -33,7 +33,6 @@ __global__ void __launch_bounds__(BLOCK) k_pilot_w(PlanDev P, DensityDev D, uint
                                                    uint64_t n, double *wbuf) {
     constexpr int M = 3 * N - 1, NE = 2 * N - 1;
     __shared__ double vlds[Dims<N>::NV * BLOCK];
-    __shared__ float rlds[Dims<N>::NV * BLOCK];
     uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     double u[2 * M], z[M];
@@ -45,7 +44,7 @@ __global__ void __launch_bounds__(BLOCK) k_pilot_w(PlanDev P, DensityDev D, uint
         return;
     }
     ea I[NE], A[NE];
-    VarsLdsEa vars{vlds + threadIdx.x, rlds + threadIdx.x, BLOCK};
+    VarsLdsEa vars{vlds + threadIdx.x, BLOCK, 0.0};
     eval_graph<ea, N>(P, z, I, A, vars);
     double w2 = 0.0, r = 0.0;
     for (int e = 0; e < NE; ++e) {

@@ -127,6 +127,31 @@ def test_eval_3_loops_against_golden(amm):
     assert np.concatenate(cert).mean() > 0.4
 
 
+def test_3_loop_sums_match_oracle_exact_values(amm):
+    """3-loop estimate path on identical counters: the accumulated sums of
+    y = I/g over the stored counters of every graph (every point recomputed in
+    double-double) against the same sums of the oracle's exact values
+    (eq. integral_approx): per insertion within 1e-12 relative to the sum of
+    |I|/g, and per class the sum and the sum of squares likewise."""
+    data = np.load(os.path.join(GOLD, 'oracle_points_3loop.npz'))
+    counters = data['counters']
+    _ctx_for(amm, 3)
+    for gi in range(len(G.se_graphs(3))):
+        g = np.ldexp(data[f'g{gi}_gx'], data[f'g{gi}_gj'])
+        y = data[f'g{gi}_I'] / g[:, None]
+        ya = np.abs(data[f'g{gi}_absI']) / g[:, None]
+        # the stored counters are two runs of 48 consecutive samples
+        amm.integrate(seed=0, n_per_graph=48, counter0=int(counters[0]), graph_begin=gi, graph_end=gi + 1,
+                      force_flag=1)
+        amm.integrate(seed=0, n_per_graph=48, counter0=int(counters[48]), graph_begin=gi, graph_end=gi + 1,
+                      force_flag=1, accumulate=1)
+        for e in range(5):
+            r = amm.read(gi, e)
+            assert r['n'] == 96 and r['n_flag'] == 96 and r['n_dd_fail'] == 0
+            assert abs(r['sum_y'] - y[:, e].sum()) <= 1e-12 * ya[:, e].sum(), (gi, e)
+            assert abs(r['sum_y2'] - (y[:, e] ** 2).sum()) <= 1e-11 * (ya[:, e] ** 2).sum(), (gi, e)
+
+
 def test_eval_empty_and_ragged(amm):
     _ctx_for(amm, 2)
     z = torch.empty((0, 5), dtype=torch.float64, device='cuda')
