@@ -393,25 +393,48 @@ template <int N> struct Dims {
 // product p = coef x_1 ... x_nv has relative error at most
 // nv (rmax + 1) + 1 (its variables, its nv roundings, the rounded
 // coefficient), and each accumulation adds |partial sum|.
+// A monomial read with one 24-byte load into registers: coefficient, number
+// of variables and their 15 index bytes (layout of Mono).
+struct MonoRegs {
+    double coef;
+    uint64_t w1, w2;       // byte 0 of w1: nv; then v[0..6] in w1, v[7..14] in w2
+    AMM_HDI int nv() const { return (int)(w1 & 0xffu); }
+    AMM_HDI int var(int i) const { return (int)(i < 7 ? (w1 >> (8 * (i + 1))) : (w2 >> (8 * (i - 7)))) & 0xff; }
+};
+AMM_HDI MonoRegs load_mono(const Mono *p) {
+    static_assert(sizeof(Mono) == 24, "Mono layout");
+    MonoRegs r;
+    __builtin_memcpy(&r, p, sizeof(Mono));
+    return r;
+}
+
 template <typename T, typename Vars>
 AMM_HDI T poly_range(const PlanDev &P, int2 r, const Vars &vars, double rmax) {
     if constexpr (std::is_same<T, ea>::value) {
         double av = 0.0, ae = 0.0;
         const double r1 = rmax + 1.0;
         for (int m = r.x; m < r.y; ++m) {
-            const Mono &mo = P.monos[m];
+            const MonoRegs mo = load_mono(P.monos + m);
+            const int nv = mo.nv();
             double p = mo.coef;
-            for (int i = 0; i < mo.nv; ++i) p = p * vars.val(mo.v[i]);
+            int i = 0;
+            for (; i + 2 <= nv; i += 2) {           // two variable reads in flight
+                const double a = vars.val(mo.var(i)), b = vars.val(mo.var(i + 1));
+                p = p * a;
+                p = p * b;
+            }
+            if (i < nv) p = p * vars.val(mo.var(i));
             av = av + p;
-            ae = fma(fabs(p), fma((double)mo.nv, r1, 1.0), ae) + fabs(av);
+            ae = fma(fabs(p), fma((double)nv, r1, 1.0), ae) + fabs(av);
         }
         return ea(av, ae);
     } else {
         T acc = T(0.0);
         for (int m = r.x; m < r.y; ++m) {
-            const Mono &mo = P.monos[m];
-            T t = mo.nv ? vars.get(mo.v[0]) : T(1.0);
-            for (int i = 1; i < mo.nv; ++i) t = t * vars.get(mo.v[i]);
+            const MonoRegs mo = load_mono(P.monos + m);
+            const int nv = mo.nv();
+            T t = nv ? vars.get(mo.var(0)) : T(1.0);
+            for (int i = 1; i < nv; ++i) t = t * vars.get(mo.var(i));
             acc = mul_add(T(mo.coef), t, acc);
         }
         return acc;
