@@ -404,7 +404,17 @@ struct MonoRegs {
 AMM_HDI MonoRegs load_mono(const Mono *p) {
     static_assert(sizeof(Mono) == 24, "Mono layout");
     MonoRegs r;
+#if defined(__HIP_DEVICE_COMPILE__)
+    // plan tables live in global memory: global loads, which (unlike flat
+    // loads) do not hold up the waits for the LDS variable reads
+    typedef const uint64_t __attribute__((address_space(1))) *gptr;
+    const gptr q = (gptr)(const void *)p;
+    r.coef = __builtin_bit_cast(double, q[0]);
+    r.w1 = q[1];
+    r.w2 = q[2];
+#else
     __builtin_memcpy(&r, p, sizeof(Mono));
+#endif
     return r;
 }
 
@@ -413,8 +423,10 @@ AMM_HDI T poly_range(const PlanDev &P, int2 r, const Vars &vars, double rmax) {
     if constexpr (std::is_same<T, ea>::value) {
         double av = 0.0, ae = 0.0;
         const double r1 = rmax + 1.0;
+        MonoRegs nxt = load_mono(P.monos + (r.x < r.y ? r.x : 0));
         for (int m = r.x; m < r.y; ++m) {
-            const MonoRegs mo = load_mono(P.monos + m);
+            const MonoRegs mo = nxt;
+            nxt = load_mono(P.monos + (m + 1 < r.y ? m + 1 : m));      // next monomial in flight
             const int nv = mo.nv();
             double p = mo.coef;
             int i = 0;
