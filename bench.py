@@ -100,6 +100,32 @@ def learned_vs_plain(ctx, tau, n):
             "pilot_s": t_pilot, "train_epochs": 300, "train_s": t_train, "loops": 3}
 
 
+def adaptive_vs_equal(ctx, tau, n, seed=0, rounds=4, floor_frac=0.25):
+    """sigma^2 * time of the adaptive split of samples over graphs (Sec. IV.C;
+    pilot n/20 per graph, then rounds split by C_j / sqrt(t_j)) against an
+    equal split of n samples per graph at the same plan cost; sigma^2 of the
+    total over graphs (eq. sigma_sum)."""
+    import torch
+    res = {}
+    for name in ('equal', 'adaptive', 'equal', 'adaptive'):                      # second pass warm
+        if name == 'equal':
+            dt = _timed(torch, lambda: ctx.integrate(seed=seed, n_per_graph=n, accept_tau=tau))
+            done = [n] * ctx.n_se
+        else:
+            box = []
+            dt = _timed(torch, lambda: box.append(ctx.integrate_adaptive(
+                seed=seed, n_pilot=max(n // 20, 1024), budget_per_graph=n, n_rounds=rounds, floor_frac=floor_frac,
+                accept_tau=tau)))
+            done = box[0]
+        tot = ctx.read(-1, -1, None)
+        res[name] = (tot['sigma'] ** 2, dt, tot['mean'], done)
+    (ve, te, me, _), (va, ta, ma, done) = res['equal'], res['adaptive']
+    return {"sigma2_time_ratio_adaptive_over_equal": (va * ta) / (ve * te), "var_equal": ve, "var_adaptive": va,
+            "s_equal": te, "s_adaptive": ta, "mean_equal": me, "mean_adaptive": ma, "samples_per_graph_equal": n,
+            "samples_per_graph_adaptive_min": min(done), "samples_per_graph_adaptive_max": max(done),
+            "rounds": rounds, "floor_frac": floor_frac, "seed": seed}
+
+
 def other_loop_orders(ctx, args):
     """Samples/s and FP64 fraction of peak at 1, 2 (generated code) and 4
     loops (74 graphs, table interpreter, one persistent launch per group,
@@ -140,11 +166,13 @@ def other_loop_orders(ctx, args):
                        "sigma_plain": ep['sigma'], "mean_learned": el['mean'], "sigma_learned": el['sigma'],
                        "pilot_samples_per_graph": 50_000, "pilot_s": t_pilot, "train_epochs": 200, "train_s": t_train,
                        "samples_per_graph": per_graph, "seed": 2}
+        adaptive = adaptive_vs_equal(ctx, tau, per_graph, seed=3) if n == 4 else None
         out[str(n)] = {"graphs": G, "samples_per_graph": per_graph, "samples_per_s": G * per_graph / dt,
                        "fp64_pass_ms": prof['ms_fp64'], "dd_ms": prof['ms_dd'],
                        "fp64_tflops": achieved / 1e12, "fp64_frac_of_peak": achieved / PEAK_FP64_VALU,
                        "flag_rate": est['n_flag'] / max(est['n'], 1), "n_dd_fail": est['n_dd_fail'],
                        "tables_build_s": t_build, "autotune": tune, "learned_vs_plain": learned,
+                       "adaptive_vs_equal": adaptive,
                        "evaluator": "generated" if n < 4 else "interpreter, fused persistent launch"}
     return out
 
@@ -252,6 +280,7 @@ def main():
     out["graph_replay_samples_per_s"] = args.steps * B * G / (time.perf_counter() - t0)
     if not args.no_learned:
         out["learned_vs_plain"] = learned_vs_plain(ctx, tau, B)
+    out["adaptive_vs_equal"] = adaptive_vs_equal(ctx, tau, B)
     if not args.no_other_orders:
         out["other_loop_orders"] = other_loop_orders(ctx, args)
     if not args.no_cpu_baseline:

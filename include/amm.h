@@ -180,6 +180,41 @@ int amm_set_option(amm_ctx *ctx, int option, int value);
 int amm_autotune(amm_ctx *ctx, const amm_run_params *run, int *blocks_per_cu, int *order_by_cost,
                  double *ms_best, void *stream);
 
+/* Sample split of one adaptive round over n graphs, Sec. IV.C (eq. for p_j):
+ * graph j receives samples in proportion to C_j / sqrt(t_j), C_j = sigma_j
+ * sqrt(N_j) being its per-sample standard deviation and t_j its cost per
+ * sample; this minimises sum_j C_j^2 / n_j (eq. sigma_sum) at the cost
+ * sum_j n_j t_j = budget.  A share floor_frac of the budget is split equally
+ * (stabilisation for graphs whose C_j is underestimated):
+ *   w_j = C_j / sqrt(t_j),
+ *   n_j = floor(floor_frac budget / sum_l t_l
+ *               + (1 - floor_frac) budget w_j / sum_l w_l t_l),
+ * evaluated in that order in FP64; if every C_j is 0 the split is equal.
+ * Inputs are host arrays of n doubles (C_j >= 0, t_j > 0, finite), budget
+ * >= 0 in the units of t, floor_frac in [0, 1]; n_out is a host array of n.
+ * Host code only: needs no device.  Errors: AMM_E_ARG. */
+int amm_adaptive_split(int n, const double *C, const double *t, double budget, double floor_frac,
+                       uint64_t *n_out);
+
+/* Adaptive distribution of samples over the graphs [graph_begin, graph_end)
+ * of `run`, Sec. IV.C.  Round 0 draws run->n_per_graph samples of every graph
+ * (counters from run->counter0; run->accumulate as in amm_integrate); each of
+ * the n_rounds - 1 later rounds takes an equal part of the budget left and
+ * splits it with amm_adaptive_split, C_j read from the accumulators so far.
+ * Graph j's samples are the consecutive counters counter0 .. counter0 +
+ * n_done[j] - 1 of its stream, so the result is that of amm_integrate calls
+ * over those ranges, and the run is deterministic.  The budget is the cost of
+ * budget_per_graph samples of every graph: sum_j n_done[j] t_j <=
+ * budget_per_graph sum_j t_j.  cost: host array of t_j (NULL = the plan's
+ * flops per sample, amm_plan_stats).  accept_tau applies unchanged in every
+ * round.  n_done: host output (may be NULL), samples per graph.  Reads the
+ * accumulators between rounds (synchronises `stream`); the last round is
+ * left enqueued.  Errors: AMM_E_ARG (budget_per_graph < n_per_graph,
+ * n_rounds < 1, floor_frac outside [0, 1], cost <= 0), AMM_E_NOTBUILT,
+ * AMM_E_HIP. */
+int amm_integrate_adaptive(amm_ctx *ctx, const amm_run_params *run, uint64_t budget_per_graph, int n_rounds,
+                           double floor_frac, const double *cost, uint64_t *n_done, void *stream);
+
 /* Round-off acceptance thresholds of eq. (interval_accept), Sec. IV.A:
  * tau_j = (1/4) sigma_j sqrt(sum_l sigma_l^2) / sum_l sigma_l over the graphs
  * [graph_begin, graph_end), where sigma_j is the current accumulators'

@@ -64,6 +64,9 @@ SYMBOLS = {
     'amm_integrate_batches': (C.c_int, [C.c_void_p, C.POINTER(RunParams), C.c_uint64, C.c_void_p]),
     'amm_autotune': (C.c_int, [C.c_void_p, C.POINTER(RunParams), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_double), C.c_void_p]),
+    'amm_adaptive_split': (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p]),
+    'amm_integrate_adaptive': (C.c_int, [C.c_void_p, C.POINTER(RunParams), C.c_uint64, C.c_int, C.c_double,
+                                         C.c_void_p, C.c_void_p, C.c_void_p]),
     'amm_read': (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Estimate)]),
     'amm_set_option': (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     'amm_accept_thresholds': (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_uint64, C.c_void_p]),
@@ -95,6 +98,15 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def adaptive_split(C_, t, budget, floor_frac):
+    """Sample split of one adaptive round (amm_adaptive_split; host code)."""
+    n = len(C_)
+    out = (C.c_uint64 * n)()
+    _check(lib().amm_adaptive_split(n, (C.c_double * n)(*C_), (C.c_double * n)(*t), float(budget),
+                                    float(floor_frac), out), 'amm_adaptive_split')
+    return list(out)
 
 
 def _check(rc, what):
@@ -214,6 +226,20 @@ class Context:
                                      blocks_per_cu, accumulate, accept_tau)
         _check(lib().amm_integrate_batches(self.h, C.byref(rp), n_batches, _stream(stream)),
                'amm_integrate_batches')
+
+    def integrate_adaptive(self, seed, n_pilot, budget_per_graph, n_rounds=4, floor_frac=0.25, cost=None,
+                           graph_begin=0, graph_end=None, counter0=0, sampler=0, blocks_per_cu=0, accumulate=0,
+                           accept_tau=None, stream=None):
+        """Adaptive split of the samples over the graphs (amm_integrate_adaptive);
+        returns the samples drawn per graph."""
+        rp, _keep = self._run_params(seed, n_pilot, graph_begin, graph_end, counter0, sampler, 0,
+                                     blocks_per_cu, accumulate, accept_tau)
+        ng = rp.graph_end - rp.graph_begin
+        done = (C.c_uint64 * ng)()
+        cst = None if cost is None else (C.c_double * ng)(*cost)
+        _check(lib().amm_integrate_adaptive(self.h, C.byref(rp), budget_per_graph, n_rounds, floor_frac, cst, done,
+                                            _stream(stream)), 'amm_integrate_adaptive')
+        return list(done)
 
     def autotune(self, seed, n_per_graph, graph_begin=0, graph_end=None, sampler=0, accept_tau=None, stream=None):
         rp, _keep = self._run_params(seed, n_per_graph, graph_begin, graph_end, 0, sampler, 0, 0, 0, accept_tau)

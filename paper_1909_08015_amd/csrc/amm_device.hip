@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -361,7 +362,8 @@ int amm_eval(amm_ctx *c, int g, const double *z, uint64_t n, double *I, double *
 // Validates a run, prepares the group buffers and stages the segment table of
 // the run on `st` (base_dev: optional device word added to every sample index).
 static int prepare_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, const uint64_t *base_dev,
-                       std::vector<SegDev> &segs, std::vector<int> &group_begin) {
+                       std::vector<SegDev> &segs, std::vector<int> &group_begin,
+                       const uint64_t *c0_per_graph = nullptr, const uint64_t *n_per_graph_arr = nullptr) {
     if (!c || !r) return fail(AMM_E_ARG, "amm_integrate: bad argument");
     if (r->graph_begin < 0 || r->graph_end > (int)c->slots.size() || r->graph_begin >= r->graph_end)
         return fail(AMM_E_ARG, "amm_integrate: bad graph range");
@@ -389,13 +391,16 @@ static int prepare_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, cons
         });
     // Segments: each graph's chunk range cut into pieces of at most one group;
     // groups: consecutive segments of distinct graphs, at most MAX_GROUP_CHUNKS.
-    const uint64_t nchunks_total = (r->n_per_graph + CHUNK - 1) / CHUNK;
     segs.clear();
     group_begin.clear();
     int gch = MAX_GROUP_CHUNKS, last_g = -1;
     for (int g : order) {
         GraphSlot &s = c->slots[g];
         bool learned = r->sampler == 1 && s.d_ptheta != nullptr;
+        const int k = g - r->graph_begin;
+        const uint64_t c0 = c0_per_graph ? c0_per_graph[k] : r->counter0;
+        const uint64_t ng = n_per_graph_arr ? n_per_graph_arr[k] : r->n_per_graph;
+        const uint64_t nchunks_total = (ng + CHUNK - 1) / CHUNK;
         for (uint64_t ch0 = 0; ch0 < nchunks_total; ch0 += MAX_GROUP_CHUNKS) {
             int nch = (int)std::min<uint64_t>(MAX_GROUP_CHUNKS, nchunks_total - ch0);
             if (gch + nch > MAX_GROUP_CHUNKS || last_g == g) {
@@ -405,8 +410,8 @@ static int prepare_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, cons
             SegDev S;
             std::memset(&S, 0, sizeof(S));
             S.A.seed = r->seed;
-            S.A.begin = r->counter0;
-            S.A.end = r->counter0 + r->n_per_graph;
+            S.A.begin = c0;
+            S.A.end = c0 + ng;
             S.A.uid = s.uid;
             S.A.chunk0 = (int)ch0;
             S.A.nchunks = nch;
@@ -473,7 +478,8 @@ static void enqueue_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, con
             ev.nseg = k1 - k0;
             for (int k = k0; k < k1; ++k) {
                 uint64_t lo = (uint64_t)segs[k].A.chunk0 * CHUNK;
-                uint64_t hi = std::min<uint64_t>(lo + (uint64_t)segs[k].A.nchunks * CHUNK, r->n_per_graph);
+                uint64_t hi = std::min<uint64_t>(lo + (uint64_t)segs[k].A.nchunks * CHUNK,
+                                                 segs[k].A.end - segs[k].A.begin);
                 ev.samples += (int64_t)(hi - lo);
             }
             evp = &ev;
@@ -622,6 +628,102 @@ int amm_autotune(amm_ctx *c, const amm_run_params *r, int *blocks_per_cu, int *o
     if (order_by_cost) *order_by_cost = best_o;
     if (ms_best) *ms_best = best;
     c->last_stream = st;
+    return AMM_OK;
+}
+
+// Sec. IV.C: the share of graph j is proportional to C_j / sqrt(t_j), which
+// minimises sum_j C_j^2 / n_j (the variance of the summed estimate, eq.
+// sigma_sum) at a fixed cost sum_j n_j t_j; a share floor_frac of the budget
+// is split equally (the stabilisation that keeps graphs with an
+// underestimated C_j sampled).  The operation order is fixed (no contraction).
+int amm_adaptive_split(int n, const double *C, const double *t, double budget, double floor_frac, uint64_t *n_out) {
+    if (n < 1 || !C || !t || !n_out || !std::isfinite(budget) || !(budget >= 0.0) || !(floor_frac >= 0.0) ||
+        !(floor_frac <= 1.0))
+        return fail(AMM_E_ARG, "amm_adaptive_split: bad argument");
+    double st = 0.0;
+    for (int j = 0; j < n; ++j) {
+        if (!std::isfinite(t[j]) || !(t[j] > 0.0) || !std::isfinite(C[j]) || !(C[j] >= 0.0))
+            return fail(AMM_E_ARG, "amm_adaptive_split: C must be >= 0 and t > 0, finite");
+        st = st + t[j];
+    }
+    std::vector<double> w(n);
+    double swt = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double r = std::sqrt(t[j]);
+        w[j] = C[j] / r;
+        const double wt = w[j] * t[j];
+        swt = swt + wt;
+    }
+    const double f = swt > 0.0 ? floor_frac : 1.0;   // all C_j = 0: equal split
+    const double eq = budget / st;
+    for (int j = 0; j < n; ++j) {
+        double x = f * eq;
+        if (swt > 0.0) {
+            double ney = budget * w[j];
+            ney = ney / swt;
+            ney = ney * (1.0 - f);
+            x = x + ney;
+        }
+        if (!(x < 9.2e18)) return fail(AMM_E_ARG, "amm_adaptive_split: sample count out of range");
+        n_out[j] = (uint64_t)std::floor(x);
+    }
+    return AMM_OK;
+}
+
+int amm_integrate_adaptive(amm_ctx *c, const amm_run_params *r, uint64_t budget_per_graph, int n_rounds,
+                           double floor_frac, const double *cost, uint64_t *n_done, void *stream) {
+    if (!c || !r || n_rounds < 1 || budget_per_graph < r->n_per_graph || !(floor_frac >= 0.0) ||
+        !(floor_frac <= 1.0))
+        return fail(AMM_E_ARG, "amm_integrate_adaptive: bad argument");
+    if (r->graph_begin < 0 || r->graph_end > (int)c->slots.size() || r->graph_begin >= r->graph_end)
+        return fail(AMM_E_ARG, "amm_integrate_adaptive: bad graph range");
+    const int gb = r->graph_begin, G = r->graph_end - r->graph_begin;
+    for (int g = gb; g < r->graph_end; ++g)
+        if (!c->slots[g].built) return fail(AMM_E_NOTBUILT, "amm_integrate_adaptive: tables not built");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<double> t(G), Cj(G);
+    double tsum = 0.0;
+    for (int j = 0; j < G; ++j) {
+        t[j] = cost ? cost[j] : c->slots[gb + j].plan.flops_per_sample;
+        if (!std::isfinite(t[j]) || !(t[j] > 0.0)) return fail(AMM_E_ARG, "amm_integrate_adaptive: cost must be > 0");
+        tsum = tsum + t[j];
+    }
+    const double total = (double)budget_per_graph * tsum;
+    std::vector<uint64_t> done(G, 0), nr(G, r->n_per_graph), c0(G);
+    double spent = 0.0;
+    amm_run_params q = *r;
+    std::vector<SegDev> segs;
+    std::vector<int> group_begin;
+    for (int round = 0; round < n_rounds; ++round) {
+        if (round > 0) {
+            // C_j = sigma_j sqrt(N_j) from the accumulators (this run's earlier rounds)
+            for (int j = 0; j < G; ++j) {
+                amm_estimate e;
+                int rc = amm_read(c, gb + j, -1, -1, -1, -1, &e);
+                if (rc) return rc;
+                Cj[j] = e.n > 0 ? e.sigma * std::sqrt((double)e.n) : 0.0;
+            }
+            const double left = total - spent;
+            if (!(left > 0.0)) break;
+            int rc = amm_adaptive_split(G, Cj.data(), t.data(), left / (double)(n_rounds - round), floor_frac,
+                                        nr.data());
+            if (rc) return rc;
+        }
+        for (int j = 0; j < G; ++j) c0[j] = r->counter0 + done[j];
+        q.accumulate = round == 0 ? r->accumulate : 1;
+        int rc = prepare_run(c, &q, st, nullptr, segs, group_begin, c0.data(), nr.data());
+        if (rc) return rc;
+        zero_acc(c, &q, st);
+        enqueue_run(c, &q, st, segs, group_begin, c->prof);
+        HIPCHK(hipGetLastError());
+        c->last_stream = st;
+        for (int j = 0; j < G; ++j) {
+            done[j] += nr[j];
+            spent = spent + (double)nr[j] * t[j];
+        }
+    }
+    if (n_done)
+        for (int j = 0; j < G; ++j) n_done[j] = done[j];
     return AMM_OK;
 }
 

@@ -1,0 +1,97 @@
+"""GPU: adaptive distribution of the samples over the graphs (Sec. IV.C).
+
+An adaptive run is a sequence of rounds whose per-graph sample ranges follow
+the oracle's split of the estimates read after the previous rounds; it must
+equal the same ranges drawn by plain runs, and lower the total variance at
+equal cost."""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip('torch')
+pytestmark = pytest.mark.gpu
+
+from oracle import schedule as S   # noqa: E402
+
+
+@pytest.fixture(scope='module')
+def amm3():
+    from paper_1909_08015_amd import Context
+    assert torch.cuda.is_available(), 'GPU tests need a GPU'
+    c = Context(0)
+    c.enumerate(3)
+    c.build_tables()
+    return c
+
+
+def _acc(amm):
+    return [amm.read(g, e) for g in range(amm.n_se) for e in range(2 * amm.loops - 1)]
+
+
+def _tau(amm, n_run, n_pilot=30_000):
+    amm.integrate(seed=1, n_per_graph=n_pilot, force_flag=1)
+    return amm.accept_thresholds(n_run)
+
+
+def test_adaptive_run_equals_its_rounds(amm3):
+    amm = amm3
+    n0, budget, f = 50_000, 150_000, 0.25
+    tau = _tau(amm, budget)
+    done = amm.integrate_adaptive(seed=7, n_pilot=n0, budget_per_graph=budget, n_rounds=2, floor_frac=f,
+                                  accept_tau=tau)
+    a = _acc(amm)
+    # replay: the pilot round, the oracle's split of its estimates, then per-graph ranges
+    t = [amm.plan_stats(g)['flops_per_sample'] for g in range(amm.n_se)]
+    amm.integrate(seed=7, n_per_graph=n0, accept_tau=tau)
+    Cj = []
+    for g in range(amm.n_se):
+        r = amm.read(g)
+        Cj.append(r['sigma'] * np.sqrt(float(r['n'])))
+    tsum = 0.0
+    for x in t:
+        tsum = tsum + x
+    spent = 0.0
+    for x in t:
+        spent = spent + float(n0) * x
+    n1 = S.split(Cj, t, S.round_budgets(float(budget) * tsum, spent, 1), f)
+    assert done == [n0 + k for k in n1]
+    assert sum(d * x for d, x in zip(done, t)) <= budget * tsum * (1 + 1e-12)
+    assert len(set(n1)) > 1                    # the split is not the equal one
+    for g in range(amm.n_se):
+        if n1[g]:
+            amm.integrate(seed=7, n_per_graph=n1[g], counter0=n0, graph_begin=g, graph_end=g + 1, accumulate=1,
+                          accept_tau=[tau[g]])
+    for x, y in zip(a, _acc(amm)):
+        assert x['n'] == y['n'] and x['n_flag'] == y['n_flag'] and x['n_dd_fail'] == y['n_dd_fail']
+        assert x['mean'] == y['mean'] and x['sigma'] == y['sigma'], (x, y)
+    # deterministic
+    assert amm.integrate_adaptive(seed=7, n_pilot=n0, budget_per_graph=budget, n_rounds=2, floor_frac=f,
+                                  accept_tau=tau, blocks_per_cu=3) == done
+    for x, y in zip(a, _acc(amm)):
+        assert x['mean'] == y['mean'] and x['sigma'] == y['sigma']
+
+
+def test_adaptive_lowers_variance_at_equal_cost(amm3):
+    amm = amm3
+    N = 2_000_000
+    tau = _tau(amm, N)
+    res = {}
+    for mode in ('equal', 'adaptive', 'equal', 'adaptive'):      # second pass timed warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == 'equal':
+            amm.integrate(seed=11, n_per_graph=N, accept_tau=tau)
+        else:
+            done = amm.integrate_adaptive(seed=11, n_pilot=N // 20, budget_per_graph=N, n_rounds=4,
+                                          floor_frac=0.25, accept_tau=tau)
+        tot = amm.read(-1, -1)
+        torch.cuda.synchronize()
+        res[mode] = (tot, time.perf_counter() - t0)
+    (te, se), (ta, sa) = res['equal'], res['adaptive']
+    var_e, var_a = te['sigma'] ** 2, ta['sigma'] ** 2
+    print(f'\n3-loop set, cost of {N} samples per graph: equal split sigma^2 {var_e:.4g} in {se * 1e3:.1f} ms, '
+          f'adaptive sigma^2 {var_a:.4g} in {sa * 1e3:.1f} ms, samples per graph {done}')
+    assert var_a < 0.9 * var_e
+    assert abs(ta['mean'] - te['mean']) <= 5.0 * np.sqrt(var_a + var_e)
+    assert sa * var_a < se * var_e
