@@ -227,7 +227,7 @@ class Context:
         _check(lib().amm_integrate_batches(self.h, C.byref(rp), n_batches, _stream(stream)),
                'amm_integrate_batches')
 
-    def integrate_adaptive(self, seed, n_pilot, budget_per_graph, n_rounds=4, floor_frac=0.25, cost=None,
+    def integrate_adaptive(self, seed, n_pilot, budget_per_graph, n_rounds=2, floor_frac=0.25, cost=None,
                            graph_begin=0, graph_end=None, counter0=0, sampler=0, blocks_per_cu=0, accumulate=0,
                            accept_tau=None, stream=None):
         """Adaptive split of the samples over the graphs (amm_integrate_adaptive);

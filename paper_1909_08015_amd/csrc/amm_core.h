@@ -440,6 +440,38 @@ AMM_HDI T poly_range(const PlanDev &P, int2 r, const Vars &vars, double rmax) {
             ae = fma(fabs(p), fma((double)nv, r1, 1.0), ae) + fabs(av);
         }
         return ea(av, ae);
+    } else if constexpr (std::is_same<T, dd>::value) {
+        // two monomials per step on separate accumulators (independent
+        // dependency chains), the next two already loading
+        dd acc0(0.0), acc1(0.0);
+        const int m0 = r.x < r.y ? r.x : 0;
+        MonoRegs na = load_mono(P.monos + m0);
+        MonoRegs nb = load_mono(P.monos + (r.x + 1 < r.y ? r.x + 1 : m0));
+        for (int m = r.x; m < r.y; m += 2) {
+            const MonoRegs a = na, b = nb;
+            const bool two = m + 1 < r.y;
+            na = load_mono(P.monos + (m + 2 < r.y ? m + 2 : m));
+            nb = load_mono(P.monos + (m + 3 < r.y ? m + 3 : m));
+            const int ka = a.nv(), kb = two ? b.nv() : 0;
+            dd ta = ka ? vars.get(a.var(0)) : dd(1.0);
+            dd tb = kb ? vars.get(b.var(0)) : dd(1.0);
+            const int kmax = ka > kb ? ka : kb;
+            for (int i = 1; i < kmax; ++i) {
+                // branch-free: past its degree a monomial reads variable 0 and
+                // multiplies by exactly 1, so both reads issue together
+                const bool ua = i < ka, ub = i < kb;
+                dd xa = vars.get(ua ? a.var(i) : 0), xb = vars.get(ub ? b.var(i) : 0);
+                xa.hi = ua ? xa.hi : 1.0;
+                xa.lo = ua ? xa.lo : 0.0;
+                xb.hi = ub ? xb.hi : 1.0;
+                xb.lo = ub ? xb.lo : 0.0;
+                ta = ta * xa;
+                tb = tb * xb;
+            }
+            acc0 = mul_add(dd(a.coef), ta, acc0);
+            if (two) acc1 = mul_add(dd(b.coef), tb, acc1);
+        }
+        return acc0 + acc1;
     } else {
         T acc = T(0.0);
         for (int m = r.x; m < r.y; ++m) {
@@ -713,12 +745,13 @@ AMM_HDI void eval_level(const PlanDev &P, const LevelDesc &d, const double *z, T
     ++sp;
 }
 
-// All insertion integrands of one SE graph at z: I[e], and sum |term| absI[e].
+// Insertion integrands of one SE graph at z summed over the forest terms
+// t0, t0 + tstep, ... (eq. for R^new): I[e], and sum |term| absI[e].
 template <typename T, int N, typename Vars>
-AMM_HDI void eval_graph(const PlanDev &P, const double *z, T *I, T *absI, Vars &vars) {
+AMM_HDI void eval_graph(const PlanDev &P, const double *z, T *I, T *absI, Vars &vars, int t0 = 0, int tstep = 1) {
     for (int e = 0; e < P.ninsert; ++e) { I[e] = T(0.0); absI[e] = T(0.0); }
     T stk[Dims<N>::DEPTH][2][N];
-    for (int t = 0; t < P.nterms; ++t) {
+    for (int t = t0; t < P.nterms; t += tstep) {
         const TermDesc td = P.terms[t];
         int sp = 0;
         T vtot = T(0.0);

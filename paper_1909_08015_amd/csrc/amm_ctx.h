@@ -24,6 +24,7 @@ constexpr int RPC = 8;                        // rounds per chunk
 constexpr int CHUNK = BLOCK * RPC;            // samples per chunk (the unit of the fixed-order sums)
 constexpr int MAX_GROUP_CHUNKS = 32768;       // chunks per group (33.5M samples): one DD pass each
 constexpr int DD_BLOCK = 64;                  // one wave per block in the double-double recompute
+constexpr int DD_RESIDENT_LANES = 65536;      // lanes of the double-double recompute resident at once (about)
 constexpr uint32_t FLAG_DDFAIL = 0x80000000u; // flag word: the DD bound cannot pass either
 constexpr double KAPPA = 2.0;                 // safety factor on the first-order running error bound
 constexpr int MAXNE = 2 * MAXN - 1;
@@ -87,6 +88,9 @@ struct amm_ctx {
     int *d_work = nullptr;              // work counter of the persistent fused kernel
     uint64_t *d_base = nullptr;         // sample base added by replays of a captured batch
     hipStream_t cap_stream = nullptr;   // internal stream for graph capture and replay
+    static constexpr int NSIDE = 4;
+    hipStream_t side[NSIDE] = {};       // the per-graph launches of a group run concurrently on these
+    hipEvent_t fork_ev = nullptr, join_ev[NSIDE] = {};
     // launch configuration (set by amm_autotune or amm_set_option)
     int use_fused = 1;                  // interpreter graphs: one persistent launch per group
     int order_by_cost = 1;              // segments of a group heaviest graph first

@@ -38,6 +38,11 @@ int fail(int code, const std::string &msg) {
 
 amm_ctx::~amm_ctx() {
     hipSetDevice(device);
+    for (int i = 0; i < NSIDE; ++i) {
+        if (side[i]) hipStreamSynchronize(side[i]), hipStreamDestroy(side[i]);
+        if (join_ev[i]) hipEventDestroy(join_ev[i]);
+    }
+    if (fork_ev) hipEventDestroy(fork_ev);
     for (auto &s : slots) {
         hipFree(s.d_levels); hipFree(s.d_terms); hipFree(s.d_ops); hipFree(s.d_monos); hipFree(s.d_ranges);
         hipFree(s.d_deg1); hipFree(s.d_deg3); hipFree(s.d_W1); hipFree(s.d_logdeg1);
@@ -184,6 +189,11 @@ int amm_create(amm_ctx **out, int device) {
     HIPCHK(hipEventCreateWithFlags(&c->seg_ev, hipEventDisableTiming));
     HIPCHK(hipMalloc((void **)&c->d_work, sizeof(int)));
     HIPCHK(hipMalloc((void **)&c->d_base, sizeof(uint64_t)));
+    for (int i = 0; i < amm_ctx::NSIDE; ++i) {
+        HIPCHK(hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
     *out = c.release();
     return AMM_OK;
 }
@@ -495,15 +505,28 @@ static void enqueue_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, con
                 case 4: hipLaunchKernelGGL(k_integrate_fused<4>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, c->d_work, c->d_part, c->d_flag, c->d_nflag); break;
             }
         } else {
+            // one launch per segment; they write disjoint chunks, so they run
+            // concurrently on the side streams (forked from and joined to st)
+            const int ns = std::min(k1 - k0, (int)amm_ctx::NSIDE);
+            if (ns > 1) {
+                hipEventRecord(c->fork_ev, st);
+                for (int i = 0; i < ns; ++i) hipStreamWaitEvent(c->side[i], c->fork_ev, 0);
+            }
             for (int k = k0; k < k1; ++k) {
                 const int grid = std::min(segs[k].A.nchunks, grid_target);
+                hipStream_t ls = ns > 1 ? c->side[(k - k0) % ns] : st;
                 switch (c->loops) {
-                    case 1: launch_seg_fp64<1>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
-                    case 2: launch_seg_fp64<2>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
-                    case 3: launch_seg_fp64<3>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
-                    case 4: launch_seg_fp64<4>(c->slots[segs[k].g], segs[k], grid, c, st, c->use_gen); break;
+                    case 1: launch_seg_fp64<1>(c->slots[segs[k].g], segs[k], grid, c, ls, c->use_gen); break;
+                    case 2: launch_seg_fp64<2>(c->slots[segs[k].g], segs[k], grid, c, ls, c->use_gen); break;
+                    case 3: launch_seg_fp64<3>(c->slots[segs[k].g], segs[k], grid, c, ls, c->use_gen); break;
+                    case 4: launch_seg_fp64<4>(c->slots[segs[k].g], segs[k], grid, c, ls, c->use_gen); break;
                 }
             }
+            if (ns > 1)
+                for (int i = 0; i < ns; ++i) {
+                    hipEventRecord(c->join_ev[i], c->side[i]);
+                    hipStreamWaitEvent(st, c->join_ev[i], 0);
+                }
         }
         if (evp) hipEventRecord(ev.b, st);
         const int grid_red = std::min(nch, grid_target);

@@ -5,7 +5,7 @@
 //                per-chunk deterministic partial sums; flagged samples are
 //                compacted per chunk in sample order
 //   k_flag_scan  offsets of the flagged samples of a launch
-//   k_dd_points  double-double recompute, one flagged sample per thread
+//   k_dd_points  double-double recompute, 1, 4 or 16 lanes per flagged sample
 //   k_dd_reduce  per-chunk sums of the recomputed samples, in flag order
 #pragma once
 #include <type_traits>
@@ -340,48 +340,86 @@ struct VarsLdsDd {
     AMM_HDI dd get(int i) const { return dd(hi[i * stride], lo[i * stride]); }
 };
 
-// Double-double recompute, one flagged sample per thread over the whole
-// group: y_e of flagged point f goes to ydd[e * cap + f]; a point that fails
-// (bound, or a non-finite value) gets NaN in ydd[f].  Points are in chunk
-// order, so the lanes of a wave nearly always share a graph's tables.
+// Double-double recompute of the flagged samples of a group with L lanes per
+// sample: lane l evaluates the forest terms l, l + L, ... and the lanes' sums
+// are added in a fixed tree, so the result does not depend on the launch.
+// y_e of flagged point f goes to ydd[e * cap + f]; a point that fails (bound,
+// or a non-finite value) gets NaN in ydd[f].
+template <int N, int L>
+__device__ __forceinline__ void dd_points_pass(const SegDev *segs, int nseg, int nch, const uint32_t *flags,
+                                               const int32_t *off, double *ydd, size_t cap, int32_t total,
+                                               double *vh, double *vl) {
+    constexpr int M = 3 * N - 1, NE = 2 * N - 1, PPB = DD_BLOCK / L;
+    static_assert(DD_BLOCK % L == 0 && (L & (L - 1)) == 0 && L <= 64, "lanes per point");
+    const int lane = threadIdx.x % L, slot = threadIdx.x / L;
+    // the trip count depends on the block only: every lane reaches the shuffles
+    for (int32_t f0 = blockIdx.x * PPB; f0 < total; f0 += gridDim.x * PPB) {
+        const int32_t f = f0 + slot;
+        bool fail = true;
+        double gx = 1.0;
+        int gj = 0;
+        dd I[NE];
+        for (int e = 0; e < NE; ++e) I[e] = dd(0.0);
+        if (f < total) {
+            int lo = 0, hi = nch;             // largest chunk with off[chunk] <= f
+            while (hi - lo > 1) {
+                int mid = (lo + hi) >> 1;
+                if (off[mid] <= f) lo = mid;
+                else hi = mid;
+            }
+            const SegDev &S = segs[seg_of_chunk(segs, nseg, lo)];
+            const uint32_t w = flags[(size_t)lo * CHUNK + (f - off[lo])];
+            fail = (w & FLAG_DDFAIL) != 0u;
+            if (!fail) {
+                uint64_t idx = base_offset(S.A) + S.A.begin + (uint64_t)(S.A.chunk0 + (lo - S.gchunk)) * CHUNK +
+                               (w & ~FLAG_DDFAIL);
+                double u[2 * M], z[M];
+                int path[M];
+                uniforms(S.A.seed, S.A.uid, idx, S.D.ptheta ? 2 * M : 2 * M - 1, u);
+                SampleOut o = sample_point<M>(S.D, u, z, path);
+                gx = o.gx;
+                gj = o.gj;
+                dd aI[NE];
+                VarsLdsDd vars{vh + threadIdx.x, vl + threadIdx.x, DD_BLOCK};
+                eval_graph<dd, N>(S.P, z, I, aI, vars, lane, L);
+            }
+        }
+        for (int e = 0; e < NE; ++e)
+            for (int d = L / 2; d > 0; d >>= 1) {
+                const dd o(__shfl_down(I[e].hi, d, L), __shfl_down(I[e].lo, d, L));
+                I[e] = I[e] + o;
+            }
+        if (f < total && lane == 0) {
+            double y[NE];
+            for (int e = 0; e < NE && !fail; ++e) {
+                y[e] = ldexp(to_double(I[e]) / gx, -gj);
+                if (!isfinite(y[e])) fail = true;
+            }
+            if (fail) {
+                ydd[f] = NAN;
+            } else {
+                for (int e = 0; e < NE; ++e) ydd[(size_t)e * cap + f] = y[e];
+            }
+        }
+    }
+}
+
+// The flagged samples of a group in double-double.  One lane per sample keeps
+// the lanes of a wave on the same table entries (points are in chunk order,
+// so a wave's points nearly always share a graph); when the samples alone
+// would leave most of the DD_RESIDENT_LANES resident lanes idle, 4 or 16
+// lanes share a sample (lower latency per pass).
 template <int N>
 __global__ void __launch_bounds__(DD_BLOCK) k_dd_points(const SegDev *segs, int nseg, int nch, const uint32_t *flags,
                                                         const int32_t *off, double *ydd, size_t cap) {
-    constexpr int M = 3 * N - 1, NE = 2 * N - 1;
     __shared__ double vh[Dims<N>::NV * DD_BLOCK], vl[Dims<N>::NV * DD_BLOCK];
     const int32_t total = off[nch];
-    for (int32_t f = blockIdx.x * DD_BLOCK + threadIdx.x; f < total; f += gridDim.x * DD_BLOCK) {
-        int lo = 0, hi = nch;                 // largest chunk with off[chunk] <= f
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (off[mid] <= f) lo = mid;
-            else hi = mid;
-        }
-        const SegDev &S = segs[seg_of_chunk(segs, nseg, lo)];
-        const uint32_t w = flags[(size_t)lo * CHUNK + (f - off[lo])];
-        bool fail = (w & FLAG_DDFAIL) != 0u;
-        double y[NE];
-        if (!fail) {
-            uint64_t idx = base_offset(S.A) + S.A.begin + (uint64_t)(S.A.chunk0 + (lo - S.gchunk)) * CHUNK +
-                           (w & ~FLAG_DDFAIL);
-            double u[2 * M], z[M];
-            int path[M];
-            uniforms(S.A.seed, S.A.uid, idx, S.D.ptheta ? 2 * M : 2 * M - 1, u);
-            SampleOut o = sample_point<M>(S.D, u, z, path);
-            dd I[NE], aI[NE];
-            VarsLdsDd vars{vh + threadIdx.x, vl + threadIdx.x, DD_BLOCK};
-            eval_graph<dd, N>(S.P, z, I, aI, vars);
-            for (int e = 0; e < NE; ++e) {
-                y[e] = ldexp(to_double(I[e]) / o.gx, -o.gj);
-                if (!isfinite(y[e])) fail = true;
-            }
-        }
-        if (fail) {
-            ydd[f] = NAN;
-        } else {
-            for (int e = 0; e < NE; ++e) ydd[(size_t)e * cap + f] = y[e];
-        }
-    }
+    if (total <= DD_RESIDENT_LANES / 16)
+        dd_points_pass<N, 16>(segs, nseg, nch, flags, off, ydd, cap, total, vh, vl);
+    else if (total <= DD_RESIDENT_LANES / 4)
+        dd_points_pass<N, 4>(segs, nseg, nch, flags, off, ydd, cap, total, vh, vl);
+    else
+        dd_points_pass<N, 1>(segs, nseg, nch, flags, off, ydd, cap, total, vh, vl);
 }
 
 // Adds the recomputed samples of each chunk to its partial sums, in flag order.
