@@ -131,6 +131,37 @@ def adaptive_vs_equal(ctx, tau, n, seed=0, rounds=2, floor_frac=0.25):
             "samples_per_graph_adaptive_max": max(done), "rounds": rounds, "floor_frac": floor_frac, "seed": seed}
 
 
+def second_calculation(ctx, n):
+    """Calc 1 (Sec. V: MRG32k3a, C2..C4 = .03/.035/.035) next to Calc 2
+    (Philox4x32-10, .03/.01/.06) on the 3-loop set, n samples per graph each:
+    samples/s of each run and the graph-by-graph combination (eq. sigma_sum
+    after combining)."""
+    import torch
+    from paper_1909_08015_amd import CALC1, CALC2
+    from paper_1909_08015_amd.amm import OPT_GENERATOR, combine
+    res = {}
+    try:
+        for name, gen, params in (('calc2', 0, CALC2), ('calc1', 1, CALC1)):
+            ctx.set_option(OPT_GENERATOR, gen)
+            ctx.build_tables(params=params)
+            ctx.integrate(seed=1, n_per_graph=100_000, force_flag=1)
+            tau = ctx.accept_thresholds(n)
+            ctx.integrate(seed=7, n_per_graph=n // 4, accept_tau=tau)                       # warm
+            dt = _timed(torch, lambda: ctx.integrate(seed=7, n_per_graph=n, accept_tau=tau))
+            per = [ctx.read(g) for g in range(ctx.n_se)]
+            tot = ctx.read(-1, -1, None)
+            res[name] = {"samples_per_s": ctx.n_se * n / dt, "mean": tot['mean'], "sigma": tot['sigma'],
+                         "means": [p['mean'] for p in per], "sigmas": [p['sigma'] for p in per]}
+    finally:
+        ctx.set_option(OPT_GENERATOR, 0)
+        ctx.build_tables(params=CALC2)
+    _, _, tm, ts = combine(res['calc1']['means'], res['calc1']['sigmas'], res['calc2']['means'],
+                           res['calc2']['sigmas'])
+    short = lambda r: {k: r[k] for k in ('samples_per_s', 'mean', 'sigma')}
+    return {"calc1_mrg32k3a": short(res['calc1']), "calc2_philox": short(res['calc2']),
+            "combined_mean": tm, "combined_sigma": ts, "samples_per_graph": n, "loops": 3}
+
+
 def other_loop_orders(ctx, args):
     """Samples/s and FP64 fraction of peak at 1, 2 (generated code) and 4
     loops (74 graphs, table interpreter, one persistent launch per group,
@@ -286,6 +317,7 @@ def main():
     if not args.no_learned:
         out["learned_vs_plain"] = learned_vs_plain(ctx, tau, B)
     out["adaptive_vs_equal"] = adaptive_vs_equal(ctx, tau, B)
+    out["second_calculation"] = second_calculation(ctx, B)
     if not args.no_other_orders:
         out["other_loop_orders"] = other_loop_orders(ctx, args)
     if not args.no_cpu_baseline:

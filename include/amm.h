@@ -164,11 +164,22 @@ int amm_integrate_batches(amm_ctx *ctx, const amm_run_params *run, uint64_t n_ba
  *   heaviest first (0: graph order).
  * AMM_OPT_BLOCKS_PER_CU (default 0 = 8): blocks per compute unit of the FP64
  *   pass when a run does not set its own.
- * None of them changes results: sums are keyed by 1024-sample chunk. */
+ * None of them changes results: sums are keyed by 1024-sample chunk.
+ * AMM_OPT_GENERATOR (default 0): pseudorandom generator of amm_sample and of
+ *   the amm_integrate* runs, 0 = Philox4x32-10 (the paper's Calc 2), 1 =
+ *   MRG32k3a (Calc 1, Sec. V).  MRG32k3a streams: graph uid starts uid 2^100
+ *   steps after a start state taken from the seed's 32-bit halves (lo, hi) as
+ *   ((1 + lo mod (m1 - 1), 12345, 12345), (1 + hi mod (m2 - 1), 12345, 12345));
+ *   sample i starts i 2^7 steps after its graph's start, and its uniform k is
+ *   ((za >> 1) 2^21 + (zb >> 11) + 1/2) 2^-52 from outputs 2k+1, 2k+2.
+ *   Sample indices must stay below 2^44 (AMM_E_ARG otherwise).  This option
+ *   changes the samples, hence the results; the pilot of the learned sampler
+ *   (amm_pilot) always uses Philox4x32-10. */
 #define AMM_OPT_GENERATED 1
 #define AMM_OPT_FUSED 2
 #define AMM_OPT_ORDER_BY_COST 3
 #define AMM_OPT_BLOCKS_PER_CU 4
+#define AMM_OPT_GENERATOR 5
 int amm_set_option(amm_ctx *ctx, int option, int value);
 
 /* Launch-configuration autotuner: times the run `run` (its n_per_graph is the
@@ -214,6 +225,19 @@ int amm_adaptive_split(int n, const double *C, const double *t, double budget, d
  * AMM_E_HIP. */
 int amm_integrate_adaptive(amm_ctx *ctx, const amm_run_params *run, uint64_t budget_per_graph, int n_rounds,
                            double floor_frac, const double *cost, uint64_t *n_done, void *stream);
+
+/* Graph-by-graph combination of two independent calculations (Sec. V: the
+ * MRG32k3a and the Philox4x32-10 runs), then the sum over graphs with eq.
+ * sigma_sum.  Per graph j the inverse-variance weighted mean
+ *   w_k = 1 / sigma_k^2,  mean = (mean1 w1 + mean2 w2) / (w1 + w2),
+ *   sigma = sqrt(1 / (w1 + w2)),
+ * evaluated in that order in FP64; a calculation with sigma 0 takes all the
+ * weight (both 0: the plain average, sigma 0).  Totals: sum of the means,
+ * sqrt of the sum of sigma^2, in graph order.  Inputs: host arrays of n
+ * doubles (sigmas >= 0).  Outputs: host arrays of n (mean, sigma) and host
+ * scalars, each may be NULL.  Host code only.  Errors: AMM_E_ARG. */
+int amm_combine(int n, const double *mean1, const double *sigma1, const double *mean2, const double *sigma2,
+                double *mean, double *sigma, double *total_mean, double *total_sigma);
 
 /* Round-off acceptance thresholds of eq. (interval_accept), Sec. IV.A:
  * tau_j = (1/4) sigma_j sqrt(sum_l sigma_l^2) / sum_l sigma_l over the graphs

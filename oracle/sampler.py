@@ -43,6 +43,8 @@ CALC2 = dict(cbigz=0.256, cbigf=0.839, cadd=0.786, csubi=0.2, csubse=0.0, csubo=
              c=(0.9, 0.03, 0.01, 0.06), d=0.75)
 # C1 = 1 - C2 - C3 - C4 evaluated once in double: 1 - 0.03 - 0.01 - 0.06
 CALC2['c'] = (((1.0 - 0.03) - 0.01) - 0.06, 0.03, 0.01, 0.06)
+# Calc 1 (Sec. V, the MRG32k3a calculation): C2, C3, C4 = 0.03, 0.035, 0.035, D = 0.75
+CALC1 = dict(CALC2, c=(((1.0 - 0.03) - 0.035) - 0.035, 0.03, 0.035, 0.035), d=0.75)
 
 
 def se_lines(n, chords):

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, 'libamm.so')
 
 AMM_OK = 0
-OPT_GENERATED, OPT_FUSED, OPT_ORDER_BY_COST, OPT_BLOCKS_PER_CU = 1, 2, 3, 4
+OPT_GENERATED, OPT_FUSED, OPT_ORDER_BY_COST, OPT_BLOCKS_PER_CU, OPT_GENERATOR = 1, 2, 3, 4, 5
 
 
 class AmmError(RuntimeError):
@@ -67,6 +67,8 @@ SYMBOLS = {
     'amm_adaptive_split': (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p]),
     'amm_integrate_adaptive': (C.c_int, [C.c_void_p, C.POINTER(RunParams), C.c_uint64, C.c_int, C.c_double,
                                          C.c_void_p, C.c_void_p, C.c_void_p]),
+    'amm_combine': (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     'amm_read': (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Estimate)]),
     'amm_set_option': (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     'amm_accept_thresholds': (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_uint64, C.c_void_p]),
@@ -109,6 +111,18 @@ def adaptive_split(C_, t, budget, floor_frac):
     return list(out)
 
 
+def combine(means1, sigmas1, means2, sigmas2):
+    """Graph-by-graph combination of two calculations (amm_combine; host
+    code): returns (per-graph means, per-graph sigmas, total mean, total sigma)."""
+    n = len(means1)
+    arr = lambda v: (C.c_double * n)(*v)
+    m, s = (C.c_double * n)(), (C.c_double * n)()
+    tm, ts = C.c_double(), C.c_double()
+    _check(lib().amm_combine(n, arr(means1), arr(sigmas1), arr(means2), arr(sigmas2), m, s, C.byref(tm),
+                             C.byref(ts)), 'amm_combine')
+    return list(m), list(s), tm.value, ts.value
+
+
 def _check(rc, what):
     if rc != AMM_OK:
         raise AmmError(f'{what} failed ({rc}): {lib().amm_last_error().decode()}')
@@ -127,6 +141,8 @@ def _stream(stream):
 
 CALC2 = dict(cbigz=0.256, cbigf=0.839, cadd=0.786, csubi=0.2, csubse=0.0, csubo=0.2,
              c=(((1.0 - 0.03) - 0.01) - 0.06, 0.03, 0.01, 0.06), d=0.75)
+# the paper's first calculation (with OPT_GENERATOR = 1, MRG32k3a)
+CALC1 = dict(CALC2, c=(((1.0 - 0.03) - 0.035) - 0.035, 0.03, 0.035, 0.035), d=0.75)
 
 
 class Context:

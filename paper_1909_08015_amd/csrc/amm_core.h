@@ -195,6 +195,72 @@ AMM_HDI void uniforms(uint64_t seed, uint32_t uid, uint64_t idx, int count, doub
     }
 }
 
+// ---------------------------------------------------------------------------
+// MRG32k3a (L'Ecuyer, Oper. Res. 47 (1999) 159) as counter-addressed streams,
+// the generator of the paper's first calculation (Sec. V).  Two order-3
+// recurrences modulo m1 = 2^32 - 209 and m2 = 2^32 - 22853, output
+// (x1 - x2) mod m1.  Sample i of a graph starts i 2^7 steps after the graph's
+// start state s (computed on the host); the jump multiplies s by table
+// powers A^(d 2^(7 + 4k)), d the k-th 4-bit digit of i (i < 2^44).
+// Uniform: ((za >> 1) 2^21 + (zb >> 11) + 1/2) 2^-52 from two outputs.
+// ---------------------------------------------------------------------------
+constexpr uint32_t MRG_M1 = 4294967087u, MRG_M2 = 4294944443u;
+constexpr uint32_t MRG_C1 = 209u, MRG_C2 = 22853u;                 // m = 2^32 - c
+constexpr uint32_t MRG_A12 = 1403580u, MRG_A13N = MRG_M1 - 810728u;
+constexpr uint32_t MRG_A21 = 527612u, MRG_A23N = MRG_M2 - 1370589u;
+constexpr int MRG_SAMPLE_SHIFT = 7, MRG_WINDOWS = 11;              // sample indices < 2^44
+constexpr int MRG_TABLE_WORDS = 2 * MRG_WINDOWS * 16 * 9;          // [component][window][digit][3][3]
+
+// t mod (2^32 - c) by folding the high word (t < 2^64, c < 2^15)
+AMM_HDI uint32_t mrg_mod(uint64_t t, uint32_t c, uint32_t m) {
+    t = (t >> 32) * c + (t & 0xffffffffull);
+    t = (t >> 32) * c + (t & 0xffffffffull);
+    return (uint32_t)(t >= m ? t - m : t);
+}
+AMM_HDI uint32_t mrg_mul(uint32_t a, uint32_t b, uint32_t c, uint32_t m) { return mrg_mod((uint64_t)a * b, c, m); }
+AMM_HDI void mrg_matvec(const uint32_t *A, uint32_t *x, uint32_t c, uint32_t m) {
+    uint32_t y[3];
+    for (int i = 0; i < 3; ++i)
+        y[i] = mrg_mod((uint64_t)mrg_mul(A[3 * i], x[0], c, m) + mrg_mul(A[3 * i + 1], x[1], c, m) +
+                           mrg_mul(A[3 * i + 2], x[2], c, m), c, m);
+    x[0] = y[0]; x[1] = y[1]; x[2] = y[2];
+}
+// one step of both components (state x[n-3], x[n-2], x[n-1]); returns z[n]
+AMM_HDI uint32_t mrg_step(uint32_t *p, uint32_t *q) {
+    const uint32_t x1 = mrg_mod((uint64_t)mrg_mul(MRG_A12, p[1], MRG_C1, MRG_M1) + mrg_mul(MRG_A13N, p[0], MRG_C1, MRG_M1),
+                                MRG_C1, MRG_M1);
+    const uint32_t x2 = mrg_mod((uint64_t)mrg_mul(MRG_A21, q[2], MRG_C2, MRG_M2) + mrg_mul(MRG_A23N, q[0], MRG_C2, MRG_M2),
+                                MRG_C2, MRG_M2);
+    p[0] = p[1]; p[1] = p[2]; p[2] = x1;
+    q[0] = q[1]; q[1] = q[2]; q[2] = x2;
+    return x1 >= x2 ? x1 - x2 : x1 + (MRG_M1 - x2);
+}
+struct MrgStream {
+    const uint32_t *tab;      // jump powers (device), MRG_TABLE_WORDS words
+    uint32_t s[6];            // graph start state: x1[n-3..n-1], x2[n-3..n-1]
+    int on;                   // 0: Philox4x32-10 instead
+};
+AMM_HDI void mrg_uniforms(const MrgStream &R, uint64_t idx, int count, double *u) {
+    uint32_t p[3] = {R.s[0], R.s[1], R.s[2]}, q[3] = {R.s[3], R.s[4], R.s[5]};
+    for (int k = 0; k < MRG_WINDOWS; ++k) {
+        const int d = (int)((idx >> (4 * k)) & 15u);
+        if (d) {
+            mrg_matvec(R.tab + (k * 16 + d) * 9, p, MRG_C1, MRG_M1);
+            mrg_matvec(R.tab + ((MRG_WINDOWS + k) * 16 + d) * 9, q, MRG_C2, MRG_M2);
+        }
+    }
+    for (int i = 0; i < count; ++i) {
+        const uint32_t za = mrg_step(p, q), zb = mrg_step(p, q);
+        const uint64_t k = ((uint64_t)(za >> 1) << 21) + (zb >> 11);
+        u[i] = ((double)k + 0.5) * 0x1p-52;
+    }
+}
+// The sample's uniforms from the run's generator.
+AMM_HDI void draw_uniforms(uint64_t seed, uint32_t uid, const MrgStream &R, uint64_t idx, int count, double *u) {
+    if (R.on) mrg_uniforms(R, idx, count, u);
+    else uniforms(seed, uid, idx, count, u);
+}
+
 AMM_HDI int popc(uint32_t x) {
     int c = 0;
     while (x) { x &= x - 1; ++c; }

@@ -88,6 +88,9 @@ struct amm_ctx {
     int *d_work = nullptr;              // work counter of the persistent fused kernel
     uint64_t *d_base = nullptr;         // sample base added by replays of a captured batch
     hipStream_t cap_stream = nullptr;   // internal stream for graph capture and replay
+    int generator = 0;                  // 0 Philox4x32-10, 1 MRG32k3a (AMM_OPT_GENERATOR)
+    uint32_t *d_mrg_tab = nullptr;      // MRG32k3a jump powers (MRG_TABLE_WORDS words)
+    uint64_t mrg_j100[2][9] = {};       // A^(2^100) of both components (graph stream spacing)
     static constexpr int NSIDE = 4;
     hipStream_t side[NSIDE] = {};       // the per-graph launches of a group run concurrently on these
     hipEvent_t fork_ev = nullptr, join_ev[NSIDE] = {};

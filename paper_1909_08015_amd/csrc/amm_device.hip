@@ -49,7 +49,7 @@ amm_ctx::~amm_ctx() {
         hipFree(s.d_ptheta); hipFree(s.d_pilotW);
     }
     hipFree(d_acc); hipFree(d_part); hipFree(d_flag); hipFree(d_nflag); hipFree(d_foff); hipFree(d_ydd);
-    hipFree(d_segs); hipFree(d_work); hipFree(d_base);
+    hipFree(d_segs); hipFree(d_work); hipFree(d_base); hipFree(d_mrg_tab);
     if (seg_ev) hipEventSynchronize(seg_ev), hipEventDestroy(seg_ev);
     if (cap_stream) hipStreamSynchronize(cap_stream), hipStreamDestroy(cap_stream);
     hipHostFree(h_segs);
@@ -60,13 +60,14 @@ amm_ctx::~amm_ctx() {
 // Kernels
 // ---------------------------------------------------------------------------
 template <int M>
-__global__ void __launch_bounds__(BLOCK) k_sample(DensityDev D, uint32_t uid, uint64_t seed, uint64_t c0, uint64_t n,
-                                                  double *z, double *gx, int32_t *gj, int32_t *path, int32_t *comp) {
+__global__ void __launch_bounds__(BLOCK) k_sample(DensityDev D, uint32_t uid, uint64_t seed, MrgStream R, uint64_t c0,
+                                                  uint64_t n, double *z, double *gx, int32_t *gj, int32_t *path,
+                                                  int32_t *comp) {
     uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     double u[2 * M], zz[M];
     int pp[M];
-    uniforms(seed, uid, c0 + i, D.ptheta ? 2 * M : 2 * M - 1, u);
+    draw_uniforms(seed, uid, R, c0 + i, D.ptheta ? 2 * M : 2 * M - 1, u);
     SampleOut o = sample_point<M>(D, u, zz, pp);
     if (z) for (int j = 0; j < M; ++j) z[i * M + j] = zz[j];
     if (path) for (int j = 0; j < M; ++j) path[i * M + j] = pp[j];
@@ -94,6 +95,88 @@ __global__ void __launch_bounds__(256) k_reduce(const double *part, int nchunks,
 __global__ void k_zero(double *p, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// MRG32k3a, host side: companion matrices, their powers, stream start states
+// (layout in amm_core.h).
+// ---------------------------------------------------------------------------
+namespace {
+struct Mat3 {
+    uint64_t a[9];
+};
+const uint64_t MRG_MOD[2] = {MRG_M1, MRG_M2};
+Mat3 mat_mul(const Mat3 &x, const Mat3 &y, uint64_t m) {
+    Mat3 r;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            uint64_t v = 0;
+            for (int k = 0; k < 3; ++k) v = (v + x.a[3 * i + k] * y.a[3 * k + j] % m) % m;
+            r.a[3 * i + j] = v;
+        }
+    return r;
+}
+Mat3 mat_id() { return Mat3{{1, 0, 0, 0, 1, 0, 0, 0, 1}}; }
+Mat3 mrg_companion(int comp) {
+    if (comp == 0) return Mat3{{0, 1, 0, 0, 0, 1, MRG_A13N, MRG_A12, 0}};
+    return Mat3{{0, 1, 0, 0, 0, 1, MRG_A23N, 0, MRG_A21}};
+}
+Mat3 mat_pow2(Mat3 a, int e, uint64_t m) {         // a^(2^e)
+    for (int i = 0; i < e; ++i) a = mat_mul(a, a, m);
+    return a;
+}
+}  // namespace
+
+// Jump table (device) and the graph spacing power A^(2^100), once per context.
+static int mrg_init(amm_ctx *c) {
+    std::vector<uint32_t> tab(MRG_TABLE_WORDS, 0u);
+    for (int comp = 0; comp < 2; ++comp) {
+        const uint64_t m = MRG_MOD[comp];
+        Mat3 w = mat_pow2(mrg_companion(comp), MRG_SAMPLE_SHIFT, m);       // A^(2^7)
+        for (int k = 0; k < MRG_WINDOWS; ++k) {
+            Mat3 p = mat_id();
+            for (int d = 0; d < 16; ++d) {
+                for (int q = 0; q < 9; ++q) tab[((comp * MRG_WINDOWS + k) * 16 + d) * 9 + q] = (uint32_t)p.a[q];
+                p = mat_mul(p, w, m);                                      // A^((d + 1) 2^(7 + 4k))
+            }
+            w = mat_pow2(w, 4, m);
+        }
+        Mat3 j = mat_pow2(mrg_companion(comp), 100, m);
+        for (int q = 0; q < 9; ++q) c->mrg_j100[comp][q] = j.a[q];
+    }
+    HIPCHK(hipMalloc((void **)&c->d_mrg_tab, tab.size() * sizeof(uint32_t)));
+    HIPCHK(hipMemcpy(c->d_mrg_tab, tab.data(), tab.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    return AMM_OK;
+}
+
+// Stream of graph uid: start state (A^(2^100))^uid s0(seed), s0 from the
+// seed's 32-bit halves.
+static MrgStream mrg_stream(const amm_ctx *c, uint64_t seed, uint32_t uid) {
+    MrgStream R;
+    R.tab = c->d_mrg_tab;
+    R.on = c->generator == 1;
+    const uint64_t half[2] = {seed & 0xffffffffull, (seed >> 32) & 0xffffffffull};
+    for (int comp = 0; comp < 2; ++comp) {
+        const uint64_t m = MRG_MOD[comp];
+        Mat3 base, p = mat_id();
+        for (int q = 0; q < 9; ++q) base.a[q] = c->mrg_j100[comp][q];
+        for (uint32_t e = uid; e; e >>= 1) {
+            if (e & 1u) p = mat_mul(p, base, m);
+            base = mat_mul(base, base, m);
+        }
+        const uint64_t s0[3] = {1 + half[comp] % (m - 1), 12345, 12345};
+        for (int i = 0; i < 3; ++i) {
+            uint64_t v = 0;
+            for (int k = 0; k < 3; ++k) v = (v + p.a[3 * i + k] * s0[k] % m) % m;
+            R.s[3 * comp + i] = (uint32_t)v;
+        }
+    }
+    return R;
+}
+
+// Sample indices of an MRG32k3a stream must stay below 2^44.
+static bool mrg_range_ok(const amm_ctx *c, uint64_t end) {
+    return c->generator != 1 || end <= (1ull << (4 * MRG_WINDOWS));
 }
 
 // ---------------------------------------------------------------------------
@@ -194,6 +277,7 @@ int amm_create(amm_ctx **out, int device) {
         HIPCHK(hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming));
     }
     HIPCHK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    if (int rc = mrg_init(c.get())) return rc;
     *out = c.release();
     return AMM_OK;
 }
@@ -334,12 +418,14 @@ int amm_sample(amm_ctx *c, int g, uint64_t seed, uint64_t c0, uint64_t n, int le
     HIPCHK(hipSetDevice(c->device));
     if (learned && !s.d_ptheta) return fail(AMM_E_ARG, "amm_sample: no sector table for the learned mixture");
     DensityDev D = s.dens_dev(learned != 0);
+    if (c0 + n < c0 || !mrg_range_ok(c, c0 + n)) return fail(AMM_E_ARG, "amm_sample: MRG32k3a sample indices >= 2^44");
+    const MrgStream R = mrg_stream(c, seed, s.uid);
     dim3 gr(grid_for(n)), bl(BLOCK);
     switch (s.M) {
-        case 2: hipLaunchKernelGGL(k_sample<2>, gr, bl, 0, st, D, s.uid, seed, c0, n, z, gx, gj, path, comp); break;
-        case 5: hipLaunchKernelGGL(k_sample<5>, gr, bl, 0, st, D, s.uid, seed, c0, n, z, gx, gj, path, comp); break;
-        case 8: hipLaunchKernelGGL(k_sample<8>, gr, bl, 0, st, D, s.uid, seed, c0, n, z, gx, gj, path, comp); break;
-        case 11: hipLaunchKernelGGL(k_sample<11>, gr, bl, 0, st, D, s.uid, seed, c0, n, z, gx, gj, path, comp); break;
+        case 2: hipLaunchKernelGGL(k_sample<2>, gr, bl, 0, st, D, s.uid, seed, R, c0, n, z, gx, gj, path, comp); break;
+        case 5: hipLaunchKernelGGL(k_sample<5>, gr, bl, 0, st, D, s.uid, seed, R, c0, n, z, gx, gj, path, comp); break;
+        case 8: hipLaunchKernelGGL(k_sample<8>, gr, bl, 0, st, D, s.uid, seed, R, c0, n, z, gx, gj, path, comp); break;
+        case 11: hipLaunchKernelGGL(k_sample<11>, gr, bl, 0, st, D, s.uid, seed, R, c0, n, z, gx, gj, path, comp); break;
         default: return fail(AMM_E_ARG, "amm_sample: unsupported M");
     }
     HIPCHK(hipGetLastError());
@@ -411,6 +497,8 @@ static int prepare_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, cons
         const uint64_t c0 = c0_per_graph ? c0_per_graph[k] : r->counter0;
         const uint64_t ng = n_per_graph_arr ? n_per_graph_arr[k] : r->n_per_graph;
         const uint64_t nchunks_total = (ng + CHUNK - 1) / CHUNK;
+        if (c0 + ng < c0 || !mrg_range_ok(c, c0 + ng))
+            return fail(AMM_E_ARG, "amm_integrate: MRG32k3a sample indices >= 2^44");
         for (uint64_t ch0 = 0; ch0 < nchunks_total; ch0 += MAX_GROUP_CHUNKS) {
             int nch = (int)std::min<uint64_t>(MAX_GROUP_CHUNKS, nchunks_total - ch0);
             if (gch + nch > MAX_GROUP_CHUNKS || last_g == g) {
@@ -429,6 +517,7 @@ static int prepare_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, cons
             for (int e = 0; e < MAXNE; ++e) S.A.cls_of[e] = e < s.ne ? s.cls_of[e] : 0;
             S.A.learned = learned ? 1 : 0;
             S.A.base_dev = base_dev;
+            S.A.mrg = mrg_stream(c, r->seed, s.uid);
             if (r->force_flag) S.A.tau = -1.0;
             else if (r->accept_tau) S.A.tau = r->accept_tau[g - r->graph_begin];
             else S.A.tau = INFINITY;
@@ -564,6 +653,9 @@ int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
 
 int amm_integrate_batches(amm_ctx *c, const amm_run_params *r, uint64_t n_batches, void *stream) {
     if (!c || !r || n_batches == 0) return fail(AMM_E_ARG, "amm_integrate_batches: bad argument");
+    if (r->n_per_graph > (~0ull - r->counter0) / n_batches ||
+        !mrg_range_ok(c, r->counter0 + n_batches * r->n_per_graph))
+        return fail(AMM_E_ARG, "amm_integrate_batches: sample indices out of range");
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(c->device));
     if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -693,6 +785,41 @@ int amm_adaptive_split(int n, const double *C, const double *t, double budget, d
     return AMM_OK;
 }
 
+int amm_combine(int n, const double *mean1, const double *sigma1, const double *mean2, const double *sigma2,
+                double *mean, double *sigma, double *total_mean, double *total_sigma) {
+    if (n < 0 || (n > 0 && (!mean1 || !sigma1 || !mean2 || !sigma2)))
+        return fail(AMM_E_ARG, "amm_combine: bad argument");
+    double tm = 0.0, tv = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double s1 = sigma1[j], s2 = sigma2[j];
+        if (!(s1 >= 0.0) || !(s2 >= 0.0)) return fail(AMM_E_ARG, "amm_combine: sigma must be >= 0");
+        double m, s;
+        if (s1 == 0.0 && s2 == 0.0) {
+            m = 0.5 * (mean1[j] + mean2[j]);
+            s = 0.0;
+        } else if (s1 == 0.0) {
+            m = mean1[j];
+            s = 0.0;
+        } else if (s2 == 0.0) {
+            m = mean2[j];
+            s = 0.0;
+        } else {
+            const double w1 = 1.0 / (s1 * s1), w2 = 1.0 / (s2 * s2);
+            const double w = w1 + w2;
+            const double a = mean1[j] * w1, b = mean2[j] * w2;
+            m = (a + b) / w;
+            s = std::sqrt(1.0 / w);
+        }
+        if (mean) mean[j] = m;
+        if (sigma) sigma[j] = s;
+        tm = tm + m;
+        tv = tv + s * s;
+    }
+    if (total_mean) *total_mean = tm;
+    if (total_sigma) *total_sigma = std::sqrt(tv);
+    return AMM_OK;
+}
+
 int amm_integrate_adaptive(amm_ctx *c, const amm_run_params *r, uint64_t budget_per_graph, int n_rounds,
                            double floor_frac, const double *cost, uint64_t *n_done, void *stream) {
     if (!c || !r || n_rounds < 1 || budget_per_graph < r->n_per_graph || !(floor_frac >= 0.0) ||
@@ -776,6 +903,9 @@ int amm_set_option(amm_ctx *c, int option, int value) {
     else if (option == AMM_OPT_BLOCKS_PER_CU) {
         if (value < 0 || value > 64) return fail(AMM_E_ARG, "amm_set_option: blocks per CU 0..64");
         c->blocks_per_cu = value;
+    } else if (option == AMM_OPT_GENERATOR) {
+        if (value != 0 && value != 1) return fail(AMM_E_ARG, "amm_set_option: generator 0 (Philox) or 1 (MRG32k3a)");
+        c->generator = value;
     } else return fail(AMM_E_ARG, "amm_set_option: unknown option");
     return AMM_OK;
 }

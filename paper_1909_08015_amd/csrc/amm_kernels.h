@@ -44,6 +44,7 @@ struct RunArgs {
     int cls_of[MAXNE];
     int learned;
     const uint64_t *base_dev;       // optional device word added to every sample index (graph replays)
+    MrgStream mrg;                  // MRG32k3a stream of the graph (mrg.on), else Philox4x32-10
 };
 
 __device__ __forceinline__ uint64_t base_offset(const RunArgs &A) { return A.base_dev ? *A.base_dev : 0ull; }
@@ -130,7 +131,7 @@ __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, c
     constexpr int M = 3 * N - 1, NE = 2 * N - 1;
     double u[2 * M], z[M];
     int path[M];
-    uniforms(A.seed, A.uid, idx, D.ptheta ? 2 * M : 2 * M - 1, u);
+    draw_uniforms(A.seed, A.uid, A.mrg, idx, D.ptheta ? 2 * M : 2 * M - 1, u);
     SampleOut o = sample_point<M>(D, u, z, path);
     ood = o.ood;
     flag = 0;
@@ -375,7 +376,7 @@ __device__ __forceinline__ void dd_points_pass(const SegDev *segs, int nseg, int
                                (w & ~FLAG_DDFAIL);
                 double u[2 * M], z[M];
                 int path[M];
-                uniforms(S.A.seed, S.A.uid, idx, S.D.ptheta ? 2 * M : 2 * M - 1, u);
+                draw_uniforms(S.A.seed, S.A.uid, S.A.mrg, idx, S.D.ptheta ? 2 * M : 2 * M - 1, u);
                 SampleOut o = sample_point<M>(S.D, u, z, path);
                 gx = o.gx;
                 gj = o.gj;

@@ -81,3 +81,22 @@ def test_combination_special_cases():
 def test_combination_sums_graphs_after_combining():
     ms, ss, tm, ts = K.combine([1.0, 2.0], [1.0, 1.0], [3.0, 2.0], [1.0, 1.0])
     assert ms == [2.0, 2.0] and tm == 4.0 and math.isclose(ts, 1.0)
+
+
+LIB = __import__('os').path.join(__import__('os').path.dirname(__import__('os').path.dirname(
+    __import__('os').path.abspath(__file__))), 'paper_1909_08015_amd', 'libamm.so')
+
+
+@pytest.mark.skipif(not __import__('os').path.exists(LIB), reason='libamm.so not built')
+def test_library_combination_matches_oracle_exactly():
+    """amm_combine is host code: callable without a GPU."""
+    from paper_1909_08015_amd.amm import combine, AmmError
+    rng = np.random.default_rng(5)
+    for trial in range(100):
+        n = int(rng.integers(1, 80))
+        m1, m2 = list(rng.normal(0, 3, n)), list(rng.normal(0, 3, n))
+        s1 = list(np.exp(rng.normal(-2, 2, n)) * (rng.random(n) > 0.05))
+        s2 = list(np.exp(rng.normal(-2, 2, n)) * (rng.random(n) > 0.05))
+        assert combine(m1, s1, m2, s2) == K.combine(m1, s1, m2, s2), trial
+    with pytest.raises(AmmError):
+        combine([1.0], [-1.0], [1.0], [1.0])
