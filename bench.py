@@ -71,6 +71,11 @@ def counters_record():
     return rec if rec.get('libamm_sha256') == sha else None
 
 
+def _progress(msg):
+    """One line per finished phase on stderr (stdout carries the JSON line)."""
+    print(f'bench: {msg}', file=sys.stderr, flush=True)
+
+
 def _timed(torch, fn):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -203,6 +208,7 @@ def other_loop_orders(ctx, args):
                        "pilot_samples_per_graph": 50_000, "pilot_s": t_pilot, "train_epochs": 200, "train_s": t_train,
                        "samples_per_graph": per_graph, "seed": 2}
         adaptive = adaptive_vs_equal(ctx, tau, per_graph, seed=3) if n == 4 else None
+        _progress(f'{n}-loop set done')
         out[str(n)] = {"graphs": G, "samples_per_graph": per_graph, "samples_per_s": G * per_graph / dt,
                        "fp64_pass_ms": prof['ms_fp64'], "dd_ms": prof['ms_dd'],
                        "fp64_tflops": achieved / 1e12, "fp64_frac_of_peak": achieved / PEAK_FP64_VALU,
@@ -224,6 +230,8 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-learned', action='store_true', help='skip the learned-sampler sigma^2*time measurement')
     ap.add_argument('--no-other-orders', action='store_true', help='skip the 1-, 2- and 4-loop measurements')
+    ap.add_argument('--no-adaptive', action='store_true', help='skip the adaptive-split sigma^2*time measurement')
+    ap.add_argument('--no-second-calc', action='store_true', help='skip the MRG32k3a (Calc 1) measurement')
     ap.add_argument('--copy-probe', type=int, default=0, metavar='BYTES',
                     help='only copy BYTES between two device buffers (calibrates HBM byte counters) and exit')
     args = ap.parse_args()
@@ -297,6 +305,9 @@ def main():
                                  (rec['fetch_bytes_per_sample'] + rec['write_bytes_per_sample']) * B),
                      "kernel": "k_integrate<3>", "kernel_ms": prof['ms_fp64'],
                      "kernel_launches": prof['launches'],
+                     # a step's 10 launches overlap on 4 streams: the duration of one
+                     # launch is the FP64 phase's span (HIP events) over its launches
+                     "launch_ms_effective": prof['ms_fp64'] / max(prof['launches'], 1),
                      "flops_per_sample": {str(g): flops[g] for g in range(G)}},
         "traffic_unit": "HBM bytes per FP64-pass launch (one graph, batch_per_graph samples), calibrated "
                         "FETCH_SIZE + WRITE_SIZE scaled from the committed counter runs of this library build",
@@ -314,10 +325,16 @@ def main():
                           accept_tau=tau)
     torch.cuda.synchronize()
     out["graph_replay_samples_per_s"] = args.steps * B * G / (time.perf_counter() - t0)
+    _progress('timed steps and graph replays done')
     if not args.no_learned:
         out["learned_vs_plain"] = learned_vs_plain(ctx, tau, B)
-    out["adaptive_vs_equal"] = adaptive_vs_equal(ctx, tau, B)
-    out["second_calculation"] = second_calculation(ctx, B)
+        _progress('learned sampler done')
+    if not args.no_adaptive:
+        out["adaptive_vs_equal"] = adaptive_vs_equal(ctx, tau, B)
+        _progress('adaptive split done')
+    if not args.no_second_calc:
+        out["second_calculation"] = second_calculation(ctx, B)
+        _progress('second calculation done')
     if not args.no_other_orders:
         out["other_loop_orders"] = other_loop_orders(ctx, args)
     if not args.no_cpu_baseline:
