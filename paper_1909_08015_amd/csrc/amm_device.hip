@@ -601,9 +601,14 @@ static void enqueue_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, con
                 hipEventRecord(c->fork_ev, st);
                 for (int i = 0; i < ns; ++i) hipStreamWaitEvent(c->side[i], c->fork_ev, 0);
             }
+            double load[amm_ctx::NSIDE] = {};
             for (int k = k0; k < k1; ++k) {
                 const int grid = std::min(segs[k].A.nchunks, grid_target);
-                hipStream_t ls = ns > 1 ? c->side[(k - k0) % ns] : st;
+                int li = 0;                   // least-loaded stream (plan cost of its launches so far)
+                for (int i = 1; i < ns; ++i)
+                    if (load[i] < load[li]) li = i;
+                load[li] += c->slots[segs[k].g].plan.flops_per_sample * (double)segs[k].A.nchunks;
+                hipStream_t ls = ns > 1 ? c->side[li] : st;
                 switch (c->loops) {
                     case 1: launch_seg_fp64<1>(c->slots[segs[k].g], segs[k], grid, c, ls, c->use_gen); break;
                     case 2: launch_seg_fp64<2>(c->slots[segs[k].g], segs[k], grid, c, ls, c->use_gen); break;

@@ -270,11 +270,20 @@ __global__ void k_reduce_grad(const float *partial, int nb, float *grad) {
     grad[p] = s;
 }
 
-__global__ void k_reduce_loss(const double *gl, int G, float *loss) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// loss = sum of the per-set losses: 256 threads sum strided slices, then a
+// fixed tree, so the value does not depend on timing
+__global__ void __launch_bounds__(256) k_reduce_loss(const double *gl, int G, float *loss) {
+    __shared__ double sh[256];
+    const int t = threadIdx.x;
     double s = 0.0;
-    for (int g = 0; g < G; ++g) s += gl[g];
-    *loss = (float)s;
+    for (int g = t; g < G; g += 256) s += gl[g];
+    sh[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    if (t == 0) *loss = (float)sh[0];
 }
 
 __global__ void k_adam(float *p, const float *g, float *m, float *v, int t, float lr) {
@@ -406,7 +415,7 @@ int loss_grad(amm_ctx *c, const float *X, const float *w, const int32_t *goff, i
                        nullptr, 0);
     hipLaunchKernelGGL(k_bwd, dim3(BW_BLOCKS), dim3(256), 0, st, c->mlp.d_params, X, h1, h2, gd, R, part);
     hipLaunchKernelGGL(k_reduce_grad, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, part, BW_BLOCKS, grad);
-    hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(1), 0, st, gl, G, loss);
+    hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(256), 0, st, gl, G, loss);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     hipFree(d); hipFree(h1); hipFree(h2); hipFree(gd); hipFree(gl); hipFree(part);
