@@ -138,7 +138,13 @@ int amm_eval(amm_ctx *ctx, int g, const double *z, uint64_t n,
              double *I, double *absI, double *bound, int precision, void *stream);
 
 /* Run the Monte Carlo (sample, evaluate, round-off check, double-double
- * recompute of flagged points, accumulate) asynchronously on `stream`. */
+ * recompute of flagged points, accumulate) asynchronously on `stream`
+ * (Sec. III.B, eq. integral_approx; Sec. IV.A).  The per-graph launches of a
+ * group run on the context's internal streams, forked from `stream` and
+ * joined back to it with events, so all work of the call is ordered before
+ * later work on `stream`.  A context is not to be used by several host
+ * threads at once.  Errors: AMM_E_ARG (bad range or parameters, sample
+ * indices out of range), AMM_E_NOTBUILT, AMM_E_HIP. */
 int amm_integrate(amm_ctx *ctx, const amm_run_params *run, void *stream);
 
 /* The same run repeated n_batches times as consecutive counter ranges:
