@@ -131,9 +131,13 @@ int amm_sample(amm_ctx *ctx, int g, uint64_t seed, uint64_t counter0, uint64_t n
 
 /* Evaluate the integrands of all 2n-1 insertions of graph g at n device
  * points z [n x M]: I [n x (2n-1)], the sum of |term| per insertion
- * absI [n x (2n-1)] and (FP64 only) the round-off bound of I, bound
- * [n x (2n-1)], from the propagated operation magnitudes (any output may be
- * NULL).  precision: 0 = FP64, 1 = double-double (value rounded to double). */
+ * absI [n x (2n-1)] and a bound [n x (2n-1)] (any output may be NULL).
+ * precision: 0 = FP64, bound = the running round-off bound of I (Sec. IV.A,
+ * eq. interval_accept); 1 = double-double (value rounded to double);
+ * 2 = FP64 interval arithmetic with outward rounding (the first interval rung
+ * of Sec. IV.A; table interpreter): I and absI are interval midpoints and
+ * bound the radius, |exact I - I| <= bound, barring overflow and underflow.
+ * Errors: AMM_E_ARG (bad graph or precision, z NULL), AMM_E_NOTBUILT. */
 int amm_eval(amm_ctx *ctx, int g, const double *z, uint64_t n,
              double *I, double *absI, double *bound, int precision, void *stream);
 

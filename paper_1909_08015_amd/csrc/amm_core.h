@@ -133,6 +133,74 @@ AMM_HDI double relerr(ea x) {
     return x.a / fabs(x.v);
 #endif
 }
+// FP64 interval [lo, hi] with outward rounding (the first interval rung of
+// Sec. IV.A's ladder).  Directed rounding is emulated from round-to-nearest:
+// the exact error of a sum (two-sum), a product (fma) or a quotient (fma
+// residual) shows on which side of the exact value the rounded result lies,
+// and a bound moves one ulp outward when it lies inside.  Every operation on
+// enclosing operands encloses the exact result, as long as nothing
+// overflows, underflows or turns NaN.
+struct iv {
+    double lo, hi;
+    AMM_HDI iv() : lo(0), hi(0) {}
+    AMM_HDI iv(double x) : lo(x), hi(x) {}
+    AMM_HDI iv(double l, double h) : lo(l), hi(h) {}
+};
+AMM_HDI double round_dn(double s, double err) { return err < 0.0 ? nextafter(s, -INFINITY) : s; }
+AMM_HDI double round_up(double s, double err) { return err > 0.0 ? nextafter(s, INFINITY) : s; }
+AMM_HDI double sum_err(double a, double b, double s) {
+    const double bb = s - a;
+    return (a - (s - bb)) + (b - bb);
+}
+AMM_HDI double add_dn(double a, double b) { const double s = a + b; return round_dn(s, sum_err(a, b, s)); }
+AMM_HDI double add_up(double a, double b) { const double s = a + b; return round_up(s, sum_err(a, b, s)); }
+AMM_HDI double mul_dn(double a, double b) { const double p = a * b; return round_dn(p, fma(a, b, -p)); }
+AMM_HDI double mul_up(double a, double b) { const double p = a * b; return round_up(p, fma(a, b, -p)); }
+// a / b = q + r / b exactly, r = a - q b (exact by fma)
+AMM_HDI double div_dn(double a, double b) {
+    const double q = a / b, r = fma(-q, b, a);
+    return (r != 0.0 && ((r < 0.0) != (b < 0.0))) ? nextafter(q, -INFINITY) : q;
+}
+AMM_HDI double div_up(double a, double b) {
+    const double q = a / b, r = fma(-q, b, a);
+    return (r != 0.0 && ((r < 0.0) == (b < 0.0))) ? nextafter(q, INFINITY) : q;
+}
+AMM_HDI iv operator+(iv x, iv y) { return iv(add_dn(x.lo, y.lo), add_up(x.hi, y.hi)); }
+AMM_HDI iv operator-(iv x) { return iv(-x.hi, -x.lo); }
+AMM_HDI iv operator-(iv x, iv y) { return x + (-y); }
+AMM_HDI iv operator*(iv x, iv y) {
+    const double l = fmin(fmin(mul_dn(x.lo, y.lo), mul_dn(x.lo, y.hi)), fmin(mul_dn(x.hi, y.lo), mul_dn(x.hi, y.hi)));
+    const double h = fmax(fmax(mul_up(x.lo, y.lo), mul_up(x.lo, y.hi)), fmax(mul_up(x.hi, y.lo), mul_up(x.hi, y.hi)));
+    return iv(l, h);
+}
+AMM_HDI iv operator/(iv x, iv y) {
+    if (y.lo <= 0.0 && y.hi >= 0.0) return iv(-INFINITY, INFINITY);
+    const double l = fmin(fmin(div_dn(x.lo, y.lo), div_dn(x.lo, y.hi)), fmin(div_dn(x.hi, y.lo), div_dn(x.hi, y.hi)));
+    const double h = fmax(fmax(div_up(x.lo, y.lo), div_up(x.lo, y.hi)), fmax(div_up(x.hi, y.lo), div_up(x.hi, y.hi)));
+    return iv(l, h);
+}
+AMM_HDI iv &operator+=(iv &x, iv y) { x = x + y; return x; }
+AMM_HDI iv &operator-=(iv &x, iv y) { x = x - y; return x; }
+AMM_HDI iv &operator*=(iv &x, iv y) { x = x * y; return x; }
+AMM_HDI double to_double(iv x) { return 0.5 * x.lo + 0.5 * x.hi; }
+AMM_HDI iv absd(iv x) {
+    if (x.lo >= 0.0) return x;
+    if (x.hi <= 0.0) return -x;
+    return iv(0.0, fmax(-x.lo, x.hi));
+}
+AMM_HDI iv mul_add(iv x, iv y, iv z) { return x * y + z; }
+AMM_HDI iv strip(iv x) { return x; }
+AMM_HDI double mag(iv x) { return fmax(fabs(x.lo), fabs(x.hi)); }
+// Half-width about the midpoint, rounded up: |exact - to_double(x)| <= radius(x).
+AMM_HDI double radius(iv x) {
+    const double m = to_double(x);
+    return fmax(add_up(x.hi, -m), add_up(m, -x.lo));
+}
+// A monomial coefficient: the double nearest a rational, so as an interval it
+// spans its two neighbours.
+template <typename T> AMM_HDI T coef_of(double c) { return T(c); }
+template <> AMM_HDI iv coef_of<iv>(double c) { return iv(nextafter(c, -INFINITY), nextafter(c, INFINITY)); }
+
 AMM_HDI double strip(double x) { return x; }
 AMM_HDI dd strip(dd x) { return x; }
 AMM_HDI double mag(double x) { return fabs(x); }
@@ -545,7 +613,7 @@ AMM_HDI T poly_range(const PlanDev &P, int2 r, const Vars &vars, double rmax) {
             const int nv = mo.nv();
             T t = nv ? vars.get(mo.var(0)) : T(1.0);
             for (int i = 1; i < nv; ++i) t = t * vars.get(mo.var(i));
-            acc = mul_add(T(mo.coef), t, acc);
+            acc = mul_add(coef_of<T>(mo.coef), t, acc);
         }
         return acc;
     }

@@ -198,8 +198,12 @@ template <int N>
 void launch_eval(const GraphSlot &gs, int g, const double *z, uint64_t n, double *I, double *a, double *b, int prec,
                  hipStream_t s, bool use_gen) {
     InterpEval EV{gs.plan_dev()};
-    if (prec) {
+    if (prec == 1) {
         launch_eval_ev<N, InterpEval, dd>(EV, z, n, I, a, b, s);
+        return;
+    }
+    if (prec == 2) {
+        launch_eval_ev<N, InterpEval, iv>(EV, z, n, I, a, b, s);
         return;
     }
     if (use_gen && gen_launch(N, g)) {
@@ -440,6 +444,7 @@ int amm_eval(amm_ctx *c, int g, const double *z, uint64_t n, double *I, double *
     if (!s.built) return fail(AMM_E_NOTBUILT, "amm_eval: tables not built");
     if (n == 0) return AMM_OK;
     if (!z) return fail(AMM_E_ARG, "amm_eval: z is NULL");
+    if (precision < 0 || precision > 2) return fail(AMM_E_ARG, "amm_eval: precision 0, 1 or 2");
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(c->device));
     PlanDev P = s.plan_dev();

@@ -1,6 +1,6 @@
 // amm_kernels.h -- Monte Carlo kernels templated on the integrand evaluator
 // (the table interpreter of amm_core.h, or a generated per-graph function).
-//   k_eval       integrands at given points (FP64 + round-off bound, or DD)
+//   k_eval       integrands at given points (FP64 + round-off bound, DD, or FP64 intervals)
 //   k_integrate  sample + evaluate + round-off check (eq. interval_accept) +
 //                per-chunk deterministic partial sums; flagged samples are
 //                compacted per chunk in sample order
@@ -91,7 +91,10 @@ __global__ void __launch_bounds__(BLOCK) k_eval(Ev EV, const double *z, uint64_t
     for (int e = 0; e < NE; ++e) {
         if (I) I[i * NE + e] = to_double(v[e]);
         if (absI) absI[i * NE + e] = to_double(a[e]);
-        if (bound) bound[i * NE + e] = KAPPA * 0x1p-53 * mag(v[e]);
+        if (bound) {
+            if constexpr (std::is_same<T, iv>::value) bound[i * NE + e] = radius(v[e]);
+            else bound[i * NE + e] = KAPPA * 0x1p-53 * mag(v[e]);
+        }
     }
 }
 
