@@ -100,3 +100,13 @@ def test_library_combination_matches_oracle_exactly():
         assert combine(m1, s1, m2, s2) == K.combine(m1, s1, m2, s2), trial
     with pytest.raises(AmmError):
         combine([1.0], [-1.0], [1.0], [1.0])
+
+
+def test_calculation_constants_are_the_papers():
+    """Sec. V: Calc 1 uses C2, C3, C4 = 0.03, 0.035, 0.035 and Calc 2 0.03, 0.01,
+    0.06, both with D = 0.75 and C1 = 1 - C2 - C3 - C4."""
+    from oracle.sampler import CALC1, CALC2
+    for params, (c2, c3, c4) in ((CALC1, (0.03, 0.035, 0.035)), (CALC2, (0.03, 0.01, 0.06))):
+        assert params['c'][1:] == (c2, c3, c4) and params['d'] == 0.75
+        assert params['c'][0] == ((1.0 - c2) - c3) - c4
+        assert abs(sum(params['c']) - 1.0) < 1e-15
