@@ -81,7 +81,7 @@ def test_adaptive_lowers_variance_at_equal_cost(amm3):
     the equal split's); the run takes about the equal split's time, and its
     estimate agrees with the equal split's."""
     amm = amm3
-    N = 8_000_000
+    N = 16_000_000
     tau = _tau(amm, N)
     amm.integrate(seed=99, n_per_graph=N, accept_tau=tau)          # independent per-graph deviations
     c2 = []
