@@ -44,7 +44,8 @@ typedef struct amm_ctx amm_ctx;
 
 /* Density constants.  Sec. III.A eq. (mc_settings): the six Deg(s)
  * constants; Sec. V: mixture weights c[0..3] = C1..C4 and D (Calc 2:
- * C2 = 0.03, C3 = 0.01, C4 = 0.06, D = 0.75, C1 = 1 - C2 - C3 - C4). */
+ * C2 = 0.03, C3 = 0.01, C4 = 0.06; Calc 1, run with AMM_OPT_GENERATOR = 1:
+ * C2 = 0.03, C3 = 0.035, C4 = 0.035; both D = 0.75, C1 = 1 - C2 - C3 - C4). */
 typedef struct {
     double cbigz, cbigf, cadd, csubi, csubse, csubo;
     double c[4];
