@@ -54,6 +54,27 @@ def test_mrg32k3a_sampling_bit_exact(mrg, n, graphs):
         assert np.array_equal(out['z'].cpu().numpy(), ref['z'])
 
 
+def test_mrg32k3a_learned_mixture_sampling_bit_exact(mrg):
+    """The learned mixture (2M uniforms per sample) on MRG32k3a streams, with a
+    seeded synthetic sector table: points, densities, paths bit-exact."""
+    amm = mrg
+    n, gi = 3, 6
+    amm.enumerate(n)
+    amm.build_tables()
+    M = 3 * n - 1
+    tab = (0.05 + 0.95 * np.random.default_rng(7).random(((1 << M), M))).astype(np.float32)
+    amm.set_sector_table(gi, tab)
+    try:
+        out = amm.sample(gi, 11, 5000, 1500, learned=1)
+        torch.cuda.synchronize()
+        d = S.Density(n, G.se_graphs(n)[gi])
+        ref = d.sample(R.uniforms(11, graph_uid(n, gi), np.arange(5000, 6500, dtype=np.uint64), 2 * M), tab)
+        for k in ('z', 'gx', 'gj', 'path', 'comp'):
+            assert np.array_equal(out[k].cpu().numpy(), ref[k]), k
+    finally:
+        amm.set_sector_table(gi, None)
+
+
 def test_mrg32k3a_index_range_is_checked(mrg):
     from paper_1909_08015_amd import AmmError
     amm = mrg
