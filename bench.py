@@ -105,7 +105,21 @@ def learned_vs_plain(ctx, tau, n):
             "pilot_s": t_pilot, "train_epochs": 300, "train_s": t_train, "loops": 3}
 
 
-def adaptive_vs_equal(ctx, tau, n, seed=0, rounds=2, floor_frac=0.25):
+def measured_costs(ctx, tau, n):
+    """t_j of Sec. IV.C as measured: seconds per sample of each graph run
+    alone (n samples, FP64 pass, recompute and reduction), after a warm-up."""
+    import torch
+    t = []
+    for g in range(ctx.n_se):
+        tg = [tau[g]] if tau is not None else None
+        ctx.integrate(seed=5, n_per_graph=max(n // 4, 1024), graph_begin=g, graph_end=g + 1, accept_tau=tg)
+        dt = _timed(torch, lambda: ctx.integrate(seed=5, n_per_graph=n, graph_begin=g, graph_end=g + 1,
+                                                 accept_tau=tg))
+        t.append(dt / n)
+    return t
+
+
+def adaptive_vs_equal(ctx, tau, n, seed=0, rounds=2, floor_frac=0.25, cost=None):
     """sigma^2 * time of the adaptive split of samples over graphs (Sec. IV.C;
     pilot n/10 per graph, then rounds split by C_j / sqrt(t_j)) against an
     equal split of n samples per graph at the same plan cost.  sigma^2 of the
@@ -123,7 +137,7 @@ def adaptive_vs_equal(ctx, tau, n, seed=0, rounds=2, floor_frac=0.25):
             box = []
             dt = _timed(torch, lambda: box.append(ctx.integrate_adaptive(
                 seed=seed, n_pilot=max(n // 10, 1024), budget_per_graph=n, n_rounds=rounds, floor_frac=floor_frac,
-                accept_tau=tau)))
+                cost=cost, accept_tau=tau)))
             done = box[0]
         tot = ctx.read(-1, -1, None)
         res[name] = (tot['sigma'] ** 2, dt, tot['mean'], done)
@@ -133,7 +147,8 @@ def adaptive_vs_equal(ctx, tau, n, seed=0, rounds=2, floor_frac=0.25):
             "implied_sigma2_time_ratio": implied * ta / te, "implied_var_ratio": implied,
             "var_equal": ve, "var_adaptive": va, "s_equal": te, "s_adaptive": ta, "mean_equal": me,
             "mean_adaptive": ma, "samples_per_graph_equal": n, "samples_per_graph_adaptive_min": min(done),
-            "samples_per_graph_adaptive_max": max(done), "rounds": rounds, "floor_frac": floor_frac, "seed": seed}
+            "samples_per_graph_adaptive_max": max(done), "rounds": rounds, "floor_frac": floor_frac, "seed": seed,
+            "cost": "plan flops per sample" if cost is None else "measured seconds per sample"}
 
 
 def second_calculation(ctx, n):
@@ -331,6 +346,7 @@ def main():
         _progress('learned sampler done')
     if not args.no_adaptive:
         out["adaptive_vs_equal"] = adaptive_vs_equal(ctx, tau, B)
+        out["adaptive_vs_equal_measured_cost"] = adaptive_vs_equal(ctx, tau, B, cost=measured_costs(ctx, tau, B // 4))
         _progress('adaptive split done')
     if not args.no_second_calc:
         out["second_calculation"] = second_calculation(ctx, B)
