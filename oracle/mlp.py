@@ -109,6 +109,18 @@ def unpack(p):
     return W1, b1, W2, b2, w3, b3
 
 
+def init_draws(seed):
+    """The NPARAM uniforms of the seeded initialisation (this library's stream
+    layout): uniform k is built from words 0 and 1 of the Philox4x32-10 block
+    with counter (k, 0, 0x4D4C50, 0) and key (seed_lo, seed_hi), converted as
+    the sampler's uniforms are."""
+    from .philox import philox4x32_10, uniform_pair, MASK
+    k = np.arange(NPARAM, dtype=np.uint64)
+    zero = np.zeros_like(k)
+    w = philox4x32_10((k, zero, zero + np.uint64(0x4D4C50), zero), (seed & MASK, (seed >> 32) & MASK))
+    return uniform_pair(w[0], w[1])
+
+
 def init_params(uniform_draws):
     """uniform_draws: NPARAM uniforms in (0,1) from the seeded generator."""
     u = np.asarray(uniform_draws, dtype=np.float64)

@@ -22,10 +22,16 @@ paper cites but does not reproduce.  Readings used here (R6-R8):
   * g2: Deg(s) = |s| (uniform sector choice, F(full) = M);
     g3: Deg3 = D*Deg1 (same sector choice as g1);
     g4: uniform sector choice with g1's continuous part;
-  * Deg1(s) = max(C_bigZ, C_bigF * w(s)) with w(s) = n_gamma(s) + n_e(s)/2
-    - 2 L(s) the minus-UV-degree of the line set in Feynman-parameter scale
-    (Speer's exponent), L(s) its cyclomatic number.  Unbiasedness does not
-    depend on this choice; only the variance does.
+  * Deg1(s) = max(C_bigZ, min(C_bigF * w(s), Deg_max)) with w(s) = n_gamma(s)
+    + n_e(s)/2 - 2 L(s) the minus-UV-degree of the line set in Feynman-parameter
+    scale (Speer's exponent), L(s) its cyclomatic number, and Deg_max = 1.
+    Unbiasedness does not depend on this choice; the variance does: near the
+    face z_s -> 0 the mixture scales like rho^(min_c Deg_c(s) - |s|) and the
+    subtracted integrand like rho^(w_f(s) - |s|), so the variance is finite
+    only if min_c Deg_c(s) < 2 w_f(s).  The smallest boundary exponent w_f
+    of the subtracted integrands is 1 (every subset of every 1-3 loop graph,
+    min over insertions), while C_bigF w(s) reaches 2.9 at 3 loops; the cap
+    keeps f/g bounded at every face.
 
 Every arithmetic step is a plain IEEE double operation in a fixed order so
 that an independent implementation of the same steps yields identical bits.
@@ -40,7 +46,7 @@ from .mathfn import amm_exp, amm_log, LN2_HI, LN2_LO, INV_LN2
 from .philox import uniforms, graph_uid
 
 CALC2 = dict(cbigz=0.256, cbigf=0.839, cadd=0.786, csubi=0.2, csubse=0.0, csubo=0.2,
-             c=(0.9, 0.03, 0.01, 0.06), d=0.75)
+             c=(0.9, 0.03, 0.01, 0.06), d=0.75, degmax=1.0)
 # C1 = 1 - C2 - C3 - C4 evaluated once in double: 1 - 0.03 - 0.01 - 0.06
 CALC2['c'] = (((1.0 - 0.03) - 0.01) - 0.06, 0.03, 0.01, 0.06)
 # Calc 1 (Sec. V, the MRG32k3a calculation): C2, C3, C4 = 0.03, 0.035, 0.035, D = 0.75
@@ -87,9 +93,12 @@ def deg_table(n, chords, params=CALC2):
     M = 3 * n - 1
     full = (1 << M) - 1
     deg = np.zeros(1 << M)
+    cap = params.get('degmax', 0.0)
     for mask in range(1, full):
-        w = omega(n, chords, mask)
-        deg[mask] = max(params['cbigz'], params['cbigf'] * w)
+        w = params['cbigf'] * omega(n, chords, mask)
+        if cap > 0.0:
+            w = min(w, cap)
+        deg[mask] = max(params['cbigz'], w)
     return deg
 
 

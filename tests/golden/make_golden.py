@@ -7,7 +7,8 @@ Calls only oracle/.  Outputs (this directory):
                                (the ends of the 1e9-sample range): the
                                oracle's z, g = gx 2^gj, component, path and the
                                exact (rational) integrands rounded to double.
-Run: python tests/golden/make_golden.py   (about 5 minutes on 8 cores)
+Run: python tests/golden/make_golden.py [--polys]   (about 5 minutes on 8
+cores; --polys derives the polynomials again instead of loading the cache)
 """
 import os
 import sys
@@ -54,11 +55,15 @@ def points_for(gi):
 
 
 def main():
-    jobs = [(n, gi) for n in (1, 2, 3) for gi in range(len(G.se_graphs(n)))]
-    with Pool(8) as pool:
-        for store in pool.imap_unordered(polys_for, jobs):
-            I._POLY_STORE.update(store)
-    I.dump_poly_cache(os.path.join(HERE, 'oracle_level_polys.json.gz'))
+    cache = os.path.join(HERE, 'oracle_level_polys.json.gz')
+    if os.path.exists(cache) and '--polys' not in sys.argv:
+        I.load_poly_cache(cache)        # the oracle's own earlier output
+    else:
+        jobs = [(n, gi) for n in (1, 2, 3) for gi in range(len(G.se_graphs(n)))]
+        with Pool(8) as pool:
+            for store in pool.imap_unordered(polys_for, jobs):
+                I._POLY_STORE.update(store)
+        I.dump_poly_cache(cache)
     print('polys', len(I._POLY_STORE), flush=True)
     with Pool(8) as pool:
         res = dict(pool.map(points_for, range(len(G.se_graphs(3)))))

@@ -12,16 +12,70 @@ from oracle import combine as K
 I3 = ((1, 0, 0), (0, 1, 0), (0, 0, 1))
 
 
+def _is_prime(n):
+    """Deterministic Miller-Rabin: the first twelve primes as bases decide
+    every n below 3.3e24."""
+    if n < 2:
+        return False
+    bases = (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37)
+    for p in bases:
+        if n % p == 0:
+            return n == p
+    d, r = n - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        r += 1
+    for a in bases:
+        x = pow(a, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(r - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+# m^3 - 1 = (m - 1)(m^2 + m + 1); both m - 1 = 2 p and m^2 + m + 1 are checked
+# below to be these products of primes.
+PERIOD_FACTORS = {R.M1: (2, 2147483543, 18446742282708232657),
+                  R.M2: (2, 2147472221, 18446547772751524693)}
+
+
 def test_component_recurrences_have_full_period_order():
     """Each component's characteristic polynomial is primitive modulo its
-    prime, so the companion matrix has order m^3 - 1: its power m^3 - 1 is the
-    identity (a wrong multiplier or modulus fails this), and the power
-    (m^3 - 1) / (m - 1) is not (it is a scalar matrix, the norm)."""
+    prime: the companion matrix has order exactly m^3 - 1, i.e. its power
+    m^3 - 1 is the identity and its power (m^3 - 1)/r is not, for every prime
+    r dividing m^3 - 1 (a wrong multiplier or modulus fails one of these)."""
     for mat, m in ((R.MAT1, R.M1), (R.MAT2, R.M2)):
+        assert _is_prime(m)
+        fac = PERIOD_FACTORS[m]
+        assert math.prod(fac) == m ** 3 - 1 and all(_is_prime(r) for r in fac)
+        assert fac[0] * fac[1] == m - 1 and fac[2] == m * m + m + 1
         assert R.mat_pow(mat, m ** 3 - 1, m) == I3
-        p = R.mat_pow(mat, (m ** 3 - 1) // (m - 1), m)
-        assert p != I3
-        assert p[0][1] == p[0][2] == p[1][0] == p[1][2] == p[2][0] == p[2][1] == 0 and p[0][0] == p[1][1] == p[2][2]
+        for r in fac:
+            assert R.mat_pow(mat, (m ** 3 - 1) // r, m) != I3, r
+
+
+def test_a_wrong_multiplier_fails_the_order_pin():
+    """Negative control: changing one multiplier of component 1 breaks the
+    order pin above."""
+    bad = [list(r) for r in R.MAT1]
+    for i in range(3):
+        for j in range(3):
+            if bad[i][j] not in (0, 1):
+                bad[i][j] = (bad[i][j] + 1) % R.M1
+                break
+        else:
+            continue
+        break
+    bad = tuple(tuple(r) for r in bad)
+    m = R.M1
+    ok = R.mat_pow(bad, m ** 3 - 1, m) == I3 and all(
+        R.mat_pow(bad, (m ** 3 - 1) // r, m) != I3 for r in PERIOD_FACTORS[m])
+    assert not ok
 
 
 def test_jump_equals_stepping():

@@ -1,0 +1,122 @@
+"""Boundary behaviour of the forest-subtracted integrands (Sec. II: the
+subtraction removes the UV and IR divergences pointwise, so every term lives
+on one simplex and the sum is integrable) and what it implies for the density
+(Sec. III.A, eq. pdf: Deg(s) controls how g scales at the face z_s -> 0).
+
+Scan: at a seeded interior base point z, the lines of a proper subset s are
+scaled z_s -> rho z_s (then renormalised to the simplex), and the exponent
+    slope(s) = d log(rho^|s| |I|) / d log rho
+is taken between rho = 1e-6 and 1e-8 in x87 extended precision.  The face is
+integrable iff slope > 0 (the measure near it is rho^(|s|-1) d rho), and y =
+f/g stays bounded there iff Deg(s) <= slope(s); the variance is finite iff the
+mixture's smallest exponent min_c Deg_c(s) < 2 slope(s)."""
+import numpy as np
+import pytest
+
+from oracle import graphs as G
+from oracle import integrand as I
+from oracle import sampler as S
+
+import os
+GOLD = os.path.join(os.path.dirname(__file__), 'golden')
+RHO = (np.longdouble('1e-6'), np.longdouble('1e-8'))
+
+
+@pytest.fixture(scope='module', autouse=True)
+def _polys():
+    I.load_poly_cache(os.path.join(GOLD, 'oracle_level_polys.json.gz'))
+
+
+def _scan_points(M, base, subsets):
+    Z = []
+    for s in subsets:
+        for r in RHO:
+            z = np.array([np.longdouble(base[i]) * (r if (s >> i) & 1 else 1) for i in range(M)], dtype=np.longdouble)
+            Z.append(z / z.sum())
+    Z = np.array(Z)
+    return [Z[:, i] for i in range(M)]
+
+
+def _slopes(vals, subsets):
+    v = np.abs(np.asarray(vals, dtype=np.longdouble)).reshape(len(subsets), 2)
+    k = np.array([bin(s).count('1') for s in subsets], dtype=np.longdouble)
+    return ((np.log(v[:, 1] * RHO[1] ** k) - np.log(v[:, 0] * RHO[0] ** k)) / np.log(RHO[1] / RHO[0])).astype(float)
+
+
+def _uv_line_sets(vg):
+    out = []
+    for a, b, kind in G.uv_subgraphs(vg):
+        if (a, b) == (0, 2 * vg.n):
+            continue
+        idx = {G.line_index(vg, seg=v) for v in range(a, b)}
+        idx |= {G.line_index(vg, chord=ci) for ci, (c, d) in enumerate(vg.chords) if a <= c and d <= b}
+        out.append(sum(1 << i for i in idx))
+    return out
+
+
+def graph_scan(n, gi, seed):
+    """Slopes of every insertion of SE graph gi over all proper subsets, and
+    of the unsubtracted term A_G f_G on the UV subgraphs' line sets."""
+    M = 3 * n - 1
+    ch = G.se_graphs(n)[gi]
+    rng = np.random.default_rng(seed)
+    base = rng.random(M) + 0.2
+    base /= base.sum()
+    subsets = list(range(1, (1 << M) - 1))
+    cols = _scan_points(M, base, subsets)
+    sub, unsub = [], []
+    with np.errstate(all='ignore'):
+        for e in range(2 * n - 1):
+            vg = G.make_vertex_graph(ch, e)
+            v, _ = I.vertex_integrand(vg, cols, exact='ld')
+            sub.append(_slopes(v, subsets))
+            uvs = _uv_line_sets(vg)
+            if uvs:
+                t0 = [t for t in G.terms(vg) if len(t.forest) == 1][0]
+                r, _ = I.term_value(vg, t0, cols, 'ld')
+                sl = _slopes(r, subsets)
+                unsub.extend(sl[s - 1] for s in uvs)
+    return subsets, np.array(sub), np.array(unsub)
+
+
+@pytest.mark.parametrize('n', [2, 3])
+def test_subtracted_integrands_are_integrable_at_every_face(n):
+    """Every proper subset of every 2- and 3-loop SE graph (30 and 254
+    subsets; 6 and 50 vertex graphs): slope >= 1 - 0.01 for the subtracted
+    integrand, while the unsubtracted A_G f_G is divergent (slope <= 0.01,
+    i.e. rho^|s| |f| does not go to zero) on the line set of every proper UV
+    subgraph (negative control: without the forest sum these faces are not
+    integrable)."""
+    n_uv = 0
+    for gi in range(len(G.se_graphs(n))):
+        subsets, sub, unsub = graph_scan(n, gi, 100 + gi)
+        assert sub.min() >= 0.99, (gi, sub.min())
+        assert np.all(unsub <= 0.01), (gi, unsub.max())
+        n_uv += len(unsub)
+    assert n_uv >= (4 if n == 2 else 40)
+
+
+@pytest.mark.parametrize('n', [2, 3])
+def test_density_exponents_keep_the_variance_finite(n):
+    """With the capped reading Deg1(s) = max(C_bigZ, min(C_bigF w(s), 1))
+    every face has Deg1(s) <= slope(s) (f/g bounded) for every insertion,
+    and every mixture component's exponent stays below 2 slope(s).  Negative
+    control at 3 loops: the uncapped Deg1 = max(C_bigZ, C_bigF w(s)) breaks
+    min_c Deg_c(s) < 2 slope(s) somewhere (infinite variance)."""
+    violations_uncapped = 0
+    for gi in range(len(G.se_graphs(n))):
+        ch = G.se_graphs(n)[gi]
+        subsets, sub, _ = graph_scan(n, gi, 200 + gi)
+        slope = sub.min(0)
+        d = S.Density(n, ch)
+        deg1 = d.deg1[subsets]
+        k = np.array([bin(s).count('1') for s in subsets], dtype=float)
+        assert np.all(deg1 > 0)
+        assert np.all(deg1 <= slope + 0.01), (gi, float((deg1 - slope).max()))
+        for degc in (deg1, S.CALC2['d'] * deg1):
+            assert np.all(degc < 2 * slope)
+        old = S.deg_table(n, ch, dict(S.CALC2, degmax=0.0))[subsets]
+        mix_old = np.minimum(np.minimum(old, S.CALC2['d'] * old), k)
+        violations_uncapped += int((mix_old >= 2 * slope - 0.01).sum())
+    if n == 3:
+        assert violations_uncapped > 0
