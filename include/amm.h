@@ -45,11 +45,19 @@ typedef struct amm_ctx amm_ctx;
 /* Density constants.  Sec. III.A eq. (mc_settings): the six Deg(s)
  * constants; Sec. V: mixture weights c[0..3] = C1..C4 and D (Calc 2:
  * C2 = 0.03, C3 = 0.01, C4 = 0.06; Calc 1, run with AMM_OPT_GENERATOR = 1:
- * C2 = 0.03, C3 = 0.035, C4 = 0.035; both D = 0.75, C1 = 1 - C2 - C3 - C4). */
+ * C2 = 0.03, C3 = 0.035, C4 = 0.035; both D = 0.75, C1 = 1 - C2 - C3 - C4).
+ * degmax caps the sector exponents of the first component:
+ *   Deg1(s) = max(cbigz, min(cbigf w(s), degmax))   (degmax <= 0: no cap),
+ * w(s) = n_photons(s) + n_electrons(s)/2 - 2 loops(s).  Near the face where
+ * the lines of s vanish the density scales like rho^(Deg(s) - |s|) and the
+ * subtracted integrand like rho^(w_f(s) - |s|) with w_f(s) >= 1, so f/g has
+ * finite variance only if Deg(s) < 2 w_f(s); the default 1.0 keeps f/g
+ * bounded at every face. */
 typedef struct {
     double cbigz, cbigf, cadd, csubi, csubse, csubo;
     double c[4];
     double d;
+    double degmax;
 } amm_density_params;
 
 /* One Monte Carlo run over a range of graphs (Sec. III.B, eq.
@@ -250,7 +258,9 @@ int amm_integrate_adaptive(amm_ctx *ctx, const amm_run_params *run, uint64_t bud
 int amm_combine(int n, const double *mean1, const double *sigma1, const double *mean2, const double *sigma2,
                 double *mean, double *sigma, double *total_mean, double *total_sigma);
 
-/* Round-off acceptance thresholds of eq. (interval_accept), Sec. IV.A:
+/* Round-off acceptance thresholds of eq. (interval_accept), Sec. IV.A (a
+ * point of graph j is accepted when the round-off bounds of its 2n-1
+ * insertion values, divided by g and added, do not exceed tau_j):
  * tau_j = (1/4) sigma_j sqrt(sum_l sigma_l^2) / sum_l sigma_l over the graphs
  * [graph_begin, graph_end), where sigma_j is the current accumulators'
  * sigma of graph j (all insertions summed; a pilot run) scaled to a run of
@@ -261,7 +271,11 @@ int amm_accept_thresholds(amm_ctx *ctx, int graph_begin, int graph_end, uint64_t
 /* Read accumulators (synchronises the last stream used).  g >= 0 selects a
  * graph; e >= 0 an insertion of it, e = -1 the sum over its insertions.
  * cls_k >= 0 with g = -1 selects a class (k, m, m') summed over all built
- * graphs (class sigma^2 adds over graphs, eq. sigma_sum). */
+ * graphs (class sigma^2 adds over graphs, eq. sigma_sum); cls_k = -1 with
+ * g = -1 gives the total over all built graphs.  The insertions of one graph
+ * are evaluated at the same points, so the sigma of a sum over insertions
+ * (e = -1, or a class) is that of the per-point sums (eq. sigma_down applied
+ * to them), which keeps the insertions' covariance. */
 int amm_read(amm_ctx *ctx, int g, int e, int cls_k, int cls_m, int cls_mp,
              amm_estimate *out);
 

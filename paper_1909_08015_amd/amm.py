@@ -21,7 +21,7 @@ class AmmError(RuntimeError):
 class DensityParams(C.Structure):
     _fields_ = [('cbigz', C.c_double), ('cbigf', C.c_double), ('cadd', C.c_double),
                 ('csubi', C.c_double), ('csubse', C.c_double), ('csubo', C.c_double),
-                ('c', C.c_double * 4), ('d', C.c_double)]
+                ('c', C.c_double * 4), ('d', C.c_double), ('degmax', C.c_double)]
 
 
 class RunParams(C.Structure):
@@ -140,7 +140,7 @@ def _stream(stream):
 
 
 CALC2 = dict(cbigz=0.256, cbigf=0.839, cadd=0.786, csubi=0.2, csubse=0.0, csubo=0.2,
-             c=(((1.0 - 0.03) - 0.01) - 0.06, 0.03, 0.01, 0.06), d=0.75)
+             c=(((1.0 - 0.03) - 0.01) - 0.06, 0.03, 0.01, 0.06), d=0.75, degmax=1.0)
 # the paper's first calculation (with OPT_GENERATOR = 1, MRG32k3a)
 CALC1 = dict(CALC2, c=(((1.0 - 0.03) - 0.035) - 0.035, 0.03, 0.035, 0.035), d=0.75)
 
@@ -185,7 +185,7 @@ class Context:
     def build_tables(self, begin=0, end=None, params=None):
         p = dict(CALC2, **(params or {}))
         dp = DensityParams(p['cbigz'], p['cbigf'], p['cadd'], p['csubi'], p['csubse'], p['csubo'],
-                           (C.c_double * 4)(*p['c']), p['d'])
+                           (C.c_double * 4)(*p['c']), p['d'], p['degmax'])
         end = self.n_se if end is None else end
         _check(lib().amm_build_tables(self.h, C.byref(dp), begin, end), 'amm_build_tables')
 

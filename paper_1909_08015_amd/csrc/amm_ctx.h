@@ -28,7 +28,10 @@ constexpr int DD_RESIDENT_LANES = 65536;      // lanes of the double-double reco
 constexpr uint32_t FLAG_DDFAIL = 0x80000000u; // flag word: the DD bound cannot pass either
 constexpr double KAPPA = 2.0;                 // safety factor on the first-order running error bound
 constexpr int MAXNE = 2 * MAXN - 1;
-constexpr int NSTAT_MAX = 3 * MAXNE + 2 * MAXNE + 4;
+// Statistics per graph: 3 per insertion, 2 per class, 2 for the per-point
+// total over the insertions, 4 counters (layout at add_stats).
+__host__ __device__ constexpr int nstat_of(int ne, int ncls) { return 3 * ne + 2 * ncls + 6; }
+constexpr int NSTAT_MAX = nstat_of(MAXNE, MAXNE);
 
 struct GraphSlot {
     bool built = false;
@@ -49,7 +52,7 @@ struct GraphSlot {
     double *d_pilotW = nullptr;               // pilot W(s, j) [2^M * M]
     // accumulators (host mirror after read)
     std::vector<double> acc;                  // NSTAT
-    int nstat() const { return 3 * ne + 2 * ncls + 4; }
+    int nstat() const { return nstat_of(ne, ncls); }
     PlanDev plan_dev() const {
         PlanDev p;
         p.levels = d_levels; p.terms = d_terms; p.ops = d_ops; p.monos = d_monos; p.ranges = d_ranges;
@@ -85,6 +88,7 @@ struct amm_ctx {
     void *h_segs = nullptr;             // pinned staging copy
     size_t seg_cap = 0;                 // capacity in segments
     hipEvent_t seg_ev = nullptr;        // recorded after the last staging copy
+    hipEvent_t run_ev = nullptr;        // recorded after the last kernel of a run (on its stream)
     int *d_work = nullptr;              // work counter of the persistent fused kernel
     uint64_t *d_base = nullptr;         // sample base added by replays of a captured batch
     hipStream_t cap_stream = nullptr;   // internal stream for graph capture and replay

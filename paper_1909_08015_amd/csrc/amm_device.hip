@@ -38,6 +38,7 @@ int fail(int code, const std::string &msg) {
 
 amm_ctx::~amm_ctx() {
     hipSetDevice(device);
+    if (run_ev) hipEventSynchronize(run_ev), hipEventDestroy(run_ev);
     for (int i = 0; i < NSIDE; ++i) {
         if (side[i]) hipStreamSynchronize(side[i]), hipStreamDestroy(side[i]);
         if (join_ev[i]) hipEventDestroy(join_ev[i]);
@@ -274,6 +275,7 @@ int amm_create(amm_ctx **out, int device) {
     HIPCHK(hipMalloc((void **)&c->d_nflag, (size_t)MAX_GROUP_CHUNKS * sizeof(int32_t)));
     HIPCHK(hipMalloc((void **)&c->d_foff, (size_t)(MAX_GROUP_CHUNKS + 1) * sizeof(int32_t)));
     HIPCHK(hipEventCreateWithFlags(&c->seg_ev, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->run_ev, hipEventDisableTiming));
     HIPCHK(hipMalloc((void **)&c->d_work, sizeof(int)));
     HIPCHK(hipMalloc((void **)&c->d_base, sizeof(uint64_t)));
     for (int i = 0; i < amm_ctx::NSIDE; ++i) {
@@ -333,7 +335,7 @@ int amm_build_tables(amm_ctx *c, const amm_density_params *params, int gb, int g
     if (c->loops > 4) return fail(AMM_E_TOOBIG, "amm_build_tables: integrand tables are built for 1..4 loops");
     amm_density_params p;
     if (params) p = *params;
-    else p = amm_density_params{0.256, 0.839, 0.786, 0.2, 0.0, 0.2, {((1.0 - 0.03) - 0.01) - 0.06, 0.03, 0.01, 0.06}, 0.75};
+    else p = amm_density_params{0.256, 0.839, 0.786, 0.2, 0.0, 0.2, {((1.0 - 0.03) - 0.01) - 0.06, 0.03, 0.01, 0.06}, 0.75, 1.0};
     HIPCHK(hipSetDevice(c->device));
     // host plans and densities: independent per graph, built on a thread pool
     {
@@ -537,6 +539,10 @@ static int prepare_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, cons
         }
     }
     group_begin.push_back((int)segs.size());
+    // The segment table, chunk partials, flags and recompute buffers are the
+    // context's: a run enqueued on another stream than the previous one waits
+    // for that run's last kernel before it restages or overwrites them.
+    HIPCHK(hipStreamWaitEvent(st, c->run_ev, 0));
     // stage the table: wait until the previous call's copy has been consumed
     HIPCHK(hipEventSynchronize(c->seg_ev));
     if (segs.size() > c->seg_cap) {
@@ -656,6 +662,7 @@ int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
     if (rc) return rc;
     zero_acc(c, r, st);
     enqueue_run(c, r, st, segs, group_begin, c->prof);
+    HIPCHK(hipEventRecord(c->run_ev, st));
     HIPCHK(hipGetLastError());
     c->last_stream = st;
     return AMM_OK;
@@ -696,6 +703,7 @@ int amm_integrate_batches(amm_ctx *c, const amm_run_params *r, uint64_t n_batche
     for (uint64_t b = 0; b < n_batches && ce == hipSuccess; ++b) ce = hipGraphLaunch(exec, cs);
     if (ce == hipSuccess) ce = hipEventRecord(e1, cs);
     if (ce == hipSuccess) ce = hipStreamWaitEvent(st, e1, 0);
+    if (ce == hipSuccess) ce = hipEventRecord(c->run_ev, st);
     hipStreamSynchronize(cs);
     if (exec) hipGraphExecDestroy(exec);
     if (graph) hipGraphDestroy(graph);
@@ -875,6 +883,7 @@ int amm_integrate_adaptive(amm_ctx *c, const amm_run_params *r, uint64_t budget_
         if (rc) return rc;
         zero_acc(c, &q, st);
         enqueue_run(c, &q, st, segs, group_begin, c->prof);
+        HIPCHK(hipEventRecord(c->run_ev, st));
         HIPCHK(hipGetLastError());
         c->last_stream = st;
         for (int j = 0; j < G; ++j) {
@@ -966,20 +975,13 @@ int amm_read(amm_ctx *c, int g, int e, int ck, int cm, int cmp, amm_estimate *ou
             out->sum_y = a[e]; out->sum_y2 = a[ne + e]; out->sum_abs = a[2 * ne + e];
             fin(out->sum_y, out->sum_y2, (double)out->n);
         } else {
-            // sum over insertions: classes carry the covariance
-            double s1 = 0, s2 = 0, sa = 0;
-            for (int q = 0; q < s.ncls; ++q) { s1 += a[3 * ne + q]; }
+            // sum over insertions: the per-point total keeps their covariance
+            double sa = 0;
             for (int q = 0; q < ne; ++q) sa += a[2 * ne + q];
-            // variance of the sum: add class variances (classes are sums at the same point)
-            double n = (double)out->n, var = 0;
-            for (int q = 0; q < s.ncls; ++q) {
-                double cs = a[3 * ne + q], cs2 = a[3 * ne + s.ncls + q];
-                var += n > 0 ? cs2 / (n * n) - cs * cs / (n * n * n) : 0.0;
-            }
-            out->sum_y = s1; out->sum_abs = sa;
-            out->mean = n > 0 ? s1 / n : 0.0;
-            out->sigma = std::sqrt(var > 0 ? var : 0.0);
-            (void)s2;
+            out->sum_y = a[3 * ne + 2 * s.ncls];
+            out->sum_y2 = a[3 * ne + 2 * s.ncls + 1];
+            out->sum_abs = sa;
+            fin(out->sum_y, out->sum_y2, (double)out->n);
         }
         return AMM_OK;
     }
@@ -992,9 +994,11 @@ int amm_read(amm_ctx *c, int g, int e, int ck, int cm, int cmp, amm_estimate *ou
         const double *a = &all[gi * NSTAT_MAX];
         int ne = s.ne, nst = s.nstat();
         double n = a[nst - 4];
-        for (int q = 0; q < s.ncls; ++q) {
+        // one class: its per-point sums; all classes: the per-point totals
+        for (int q = 0; q < (ck >= 0 ? s.ncls : 1); ++q) {
             if (ck >= 0 && (s.cls_kmm[q][0] != ck || s.cls_kmm[q][1] != cm || s.cls_kmm[q][2] != cmp)) continue;
-            double cs = a[3 * ne + q], cs2 = a[3 * ne + s.ncls + q];
+            const double cs = ck >= 0 ? a[3 * ne + q] : a[3 * ne + 2 * s.ncls];
+            const double cs2 = ck >= 0 ? a[3 * ne + s.ncls + q] : a[3 * ne + 2 * s.ncls + 1];
             if (n > 0) {
                 mean += cs / n;
                 double v = cs2 / (n * n) - cs * cs / (n * n * n);

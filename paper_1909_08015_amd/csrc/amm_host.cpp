@@ -562,7 +562,7 @@ std::string poly_key(const std::vector<Item> &items, int op) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Density tables (Sec. III.A readings: Deg1 = max(C_bigZ, C_bigF w(s)))
+// Density tables (Sec. III.A readings: Deg1 = max(C_bigZ, min(C_bigF w(s), Deg_max)))
 // ---------------------------------------------------------------------------
 void set_stats(const SEGraph &g, uint32_t mask, int *loops_out, int *comps_out, int *ng_out, int *ne_out) {
     int n = g.n, M = 3 * n - 1;
@@ -637,8 +637,9 @@ void build_density(const SEGraph &g, const amm_density_params &p, DensityTables 
     d.logdeg1.assign(1u << M, 0.0);
     std::vector<double> F(1u << M, 0.0);
     for (uint32_t m = 1; m < full; ++m) {
-        double w = omega_set(g, m);
-        d.deg1[m] = std::max(p.cbigz, p.cbigf * w);
+        double w = p.cbigf * omega_set(g, m);
+        if (p.degmax > 0.0) w = std::min(w, p.degmax);
+        d.deg1[m] = std::max(p.cbigz, w);
         d.deg3[m] = p.d * d.deg1[m];
         d.logdeg1[m] = host_log(d.deg1[m]);
     }

@@ -103,9 +103,12 @@ __global__ void __launch_bounds__(BLOCK) k_eval(Ev EV, const double *z, uint64_t
 // Statistic layout per graph:
 //   [0, ne)        sum y_e       [ne, 2ne)  sum y_e^2     [2ne, 3ne) sum |y_e|
 //   [3ne, 3ne+c)   sum y_class   [.., +c)   sum y_class^2
+//   [3ne+2c]       sum y_tot     [3ne+2c+1] sum y_tot^2   (y_tot = sum_e y_e)
 //   then n, n_flag, n_dd_fail, n_ood.
+// The insertions of a point share it, so the variance of a class or of the
+// graph's total is that of the per-point sum (eq. sigma_down applied to it).
 template <int N>
-__device__ __forceinline__ void add_stats(double (&st)[3 * (2 * N - 1) + 2 * (2 * N - 1) + 4], const double *y,
+__device__ __forceinline__ void add_stats(double (&st)[nstat_of(2 * N - 1, 2 * N - 1)], const double *y,
                                           const RunArgs &A) {
     constexpr int NE = 2 * N - 1;
     double yc[NE];
@@ -117,11 +120,15 @@ __device__ __forceinline__ void add_stats(double (&st)[3 * (2 * N - 1) + 2 * (2 
         for (int c = 0; c < NE; ++c)
             if (A.cls_of[e] == c) yc[c] += y[e];
     }
+    double yt = 0.0;
     for (int c = 0; c < NE; ++c) {
         if (c >= A.ncls) break;
         st[3 * NE + c] += yc[c];
         st[3 * NE + A.ncls + c] += yc[c] * yc[c];
     }
+    for (int e = 0; e < NE; ++e) yt += y[e];
+    st[3 * NE + 2 * A.ncls] += yt;
+    st[3 * NE + 2 * A.ncls + 1] += yt * yt;
 }
 
 // One sample: point, density, FP64 integrands with their round-off bound and
@@ -165,16 +172,20 @@ __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, c
             VarsPriv<ea, 1> vars;
             EV.template eval<ea, N>(z, I, aI, vars);
         }
+        // the graph's threshold bounds the round-off of the point's total over
+        // its insertions: the bounds of the insertions add
+        double r = 0.0;
         for (int e = 0; e < NE; ++e) {
             double ye = ldexp(I[e].v / o.gx, -o.gj);
-            double r = ldexp(I[e].a / o.gx, -o.gj);
-            if (!(KAPPA * 0x1p-53 * r <= A.tau) || !isfinite(ye)) flag = 1;
-            // hopeless for double-double only when the bound is finite and too
-            // large even at the double-double unit (a non-finite bound says nothing)
-            if (A.tau >= 0.0 && isfinite(r) && !(KAPPA * 0x1p-104 * r <= A.tau)) ddbad = 1;
-            if constexpr (N == 1) ddbad = 1;        // no double-double recompute at one loop (disabled)
+            r += ldexp(I[e].a / o.gx, -o.gj);
+            if (!isfinite(ye)) flag = 1;
             y[e] = ye;
         }
+        if (!(KAPPA * 0x1p-53 * r <= A.tau)) flag = 1;
+        // hopeless for double-double only when the bound is finite and too
+        // large even at the double-double unit (a non-finite bound says nothing)
+        if (A.tau >= 0.0 && isfinite(r) && !(KAPPA * 0x1p-104 * r <= A.tau)) ddbad = 1;
+        if constexpr (N == 1) ddbad = 1;            // no double-double recompute at one loop (disabled)
     }
     if (flag)
         for (int e = 0; e < NE; ++e) y[e] = 0.0;
@@ -213,12 +224,12 @@ __device__ __forceinline__ void block_stats(const double (&st)[NST], int nst, do
 template <int N, class Ev>
 __device__ __forceinline__ void process_chunk(const Ev &EV, const DensityDev &D, const RunArgs &A, int ch,
                                               double *part_ch, uint32_t *flags_ch, int32_t *nflag_ch,
-                                              double (*shs)[3 * (2 * N - 1) + 2 * (2 * N - 1) + 4], int *shw,
+                                              double (*shs)[nstat_of(2 * N - 1, 2 * N - 1)], int *shw,
                                               double *vlds) {
     constexpr int NE = 2 * N - 1;
-    constexpr int NST = 3 * NE + 2 * NE + 4;
+    constexpr int NST = nstat_of(NE, NE);
     constexpr int NW = BLOCK / 64;
-    const int nst = 3 * NE + 2 * A.ncls + 4;
+    const int nst = nstat_of(NE, A.ncls);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double st[NST];
     for (int s = 0; s < NST; ++s) st[s] = 0.0;
@@ -258,7 +269,7 @@ template <int N, class Ev>
 __global__ void __launch_bounds__(BLOCK) k_integrate(Ev EV, DensityDev D, RunArgs A, double *part, uint32_t *flags,
                                                      int32_t *nflag) {
     constexpr int NE = 2 * N - 1;
-    constexpr int NST = 3 * NE + 2 * NE + 4;
+    constexpr int NST = nstat_of(NE, NE);
     __shared__ double shs[BLOCK / 64][NST];
     __shared__ int shw[BLOCK / 64];
     __shared__ double vlds[(Ev::kLds ? Dims<N>::NV : 1) * BLOCK];
@@ -275,7 +286,7 @@ template <int N>
 __global__ void __launch_bounds__(BLOCK) k_integrate_fused(const SegDev *segs, int nseg, int nch, int *work,
                                                            double *part, uint32_t *flags, int32_t *nflag) {
     constexpr int NE = 2 * N - 1;
-    constexpr int NST = 3 * NE + 2 * NE + 4;
+    constexpr int NST = nstat_of(NE, NE);
     __shared__ double shs[BLOCK / 64][NST];
     __shared__ int shw[BLOCK / 64];
     __shared__ double vlds[Dims<N>::NV * BLOCK];
@@ -431,13 +442,13 @@ template <int N>
 __global__ void __launch_bounds__(BLOCK) k_dd_reduce(const SegDev *segs, int nseg, int nch, const int32_t *off,
                                                      const double *ydd, size_t cap, double *part) {
     constexpr int NE = 2 * N - 1;
-    constexpr int NST = 3 * NE + 2 * NE + 4;
+    constexpr int NST = nstat_of(NE, NE);
     __shared__ double shs[BLOCK / 64][NST];
     for (int ch = blockIdx.x; ch < nch; ch += gridDim.x) {
         const int32_t a = off[ch], b = off[ch + 1];
         if (a == b) continue;                 // uniform over the block
         const RunArgs &A = segs[seg_of_chunk(segs, nseg, ch)].A;
-        const int nst = 3 * NE + 2 * A.ncls + 4;
+        const int nst = nstat_of(NE, A.ncls);
         double st[NST];
         for (int s = 0; s < NST; ++s) st[s] = 0.0;
         for (int32_t f = a + threadIdx.x; f < b; f += BLOCK) {
