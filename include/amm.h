@@ -171,6 +171,24 @@ int amm_integrate(amm_ctx *ctx, const amm_run_params *run, void *stream);
  * Errors: AMM_E_ARG, AMM_E_NOTBUILT, AMM_E_HIP. */
 int amm_integrate_batches(amm_ctx *ctx, const amm_run_params *run, uint64_t n_batches, void *stream);
 
+/* Caller-owned device workspace for the Monte Carlo runs (amm_integrate,
+ * amm_integrate_batches, amm_integrate_adaptive, amm_autotune), so that a
+ * framework's allocator (e.g. PyTorch) can supply the device memory: the
+ * per-group chunk partial sums, flag words and double-double results.
+ * dev_ptr: device memory of the context's device, 256-byte aligned, of
+ * `bytes` bytes, owned by the caller, never freed by the context, and not to
+ * be used by the caller while runs of the context are pending.  The group size
+ * becomes the largest chunk count c (1024 samples each, c <= 32768) with
+ * amm_workspace_bytes(c) <= bytes; results do not depend on it beyond the
+ * order in which segment sums are added.  The context frees its own group
+ * buffers; dev_ptr NULL returns to them (allocated again on the next run).
+ * Waits for the context's last run.  Errors: AMM_E_ARG (misaligned, or
+ * smaller than amm_workspace_bytes(1)), AMM_E_HIP. */
+int amm_set_workspace(amm_ctx *ctx, void *dev_ptr, size_t bytes);
+/* Bytes of a workspace for groups of chunks_per_group chunks (1 .. 32768;
+ * any loop order), 0 for a count out of range. */
+size_t amm_workspace_bytes(int chunks_per_group);
+
 /* Options (value semantics per option):
  * AMM_OPT_GENERATED (default 1): evaluate integrands with the straight-line
  *   code generated at build time for the graph when it exists (1-3 loops),

@@ -84,6 +84,8 @@ SYMBOLS = {
     'amm_mlp_loss_grad': (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
     'amm_set_sector_table': (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    'amm_set_workspace': (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    'amm_workspace_bytes': (C.c_size_t, [C.c_int]),
 }
 
 
@@ -235,6 +237,20 @@ class Context:
         rp, _keep = self._run_params(seed, n_per_graph, graph_begin, graph_end, counter0, sampler, force_flag,
                                      blocks_per_cu, accumulate, accept_tau)
         _check(lib().amm_integrate(self.h, C.byref(rp), _stream(stream)), 'amm_integrate')
+
+    def set_workspace(self, tensor=None):
+        """Caller-owned device workspace (a torch tensor kept alive by the
+        caller); None returns to the context's own buffers."""
+        if tensor is None:
+            _check(lib().amm_set_workspace(self.h, None, 0), 'amm_set_workspace')
+        else:
+            nbytes = tensor.numel() * tensor.element_size()
+            _check(lib().amm_set_workspace(self.h, _ptr(tensor), nbytes), 'amm_set_workspace')
+        self._workspace = tensor
+
+    @staticmethod
+    def workspace_bytes(chunks_per_group):
+        return int(lib().amm_workspace_bytes(chunks_per_group))
 
     def integrate_batches(self, seed, n_per_graph, n_batches, graph_begin=0, graph_end=None, counter0=0,
                           sampler=0, force_flag=0, blocks_per_cu=0, accumulate=0, accept_tau=None, stream=None):

@@ -33,6 +33,44 @@ constexpr int MAXNE = 2 * MAXN - 1;
 __host__ __device__ constexpr int nstat_of(int ne, int ncls) { return 3 * ne + 2 * ncls + 6; }
 constexpr int NSTAT_MAX = nstat_of(MAXNE, MAXNE);
 
+// Scratch of a Monte Carlo run, used one group of chunks at a time: chunk
+// partial sums, flag words, flag counts and their scan, the double-double
+// results of the group's flagged points (room for every point) and the work
+// counter of the fused launch.
+struct Workspace {
+    double *part = nullptr;     // [max_chunks * NSTAT_MAX]
+    uint32_t *flag = nullptr;   // [max_chunks * CHUNK]
+    int32_t *nflag = nullptr;   // [max_chunks]
+    int32_t *foff = nullptr;    // [max_chunks + 1]
+    double *ydd = nullptr;      // [ydd_ne][max_chunks * CHUNK]
+    int *work = nullptr;        // [1]
+    int max_chunks = 0;         // chunks per group (<= MAX_GROUP_CHUNKS)
+    int ydd_ne = 0;             // insertions the ydd region holds
+    size_t ydd_cap() const { return (size_t)max_chunks * CHUNK; }
+};
+
+// Byte layout of a workspace carved from one region (256-byte aligned parts).
+constexpr size_t ws_align(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t ws_bytes(int max_chunks, int ne) {
+    return ws_align((size_t)max_chunks * NSTAT_MAX * sizeof(double)) +
+           ws_align((size_t)max_chunks * CHUNK * sizeof(uint32_t)) + ws_align((size_t)max_chunks * sizeof(int32_t)) +
+           ws_align((size_t)(max_chunks + 1) * sizeof(int32_t)) +
+           ws_align((size_t)ne * max_chunks * CHUNK * sizeof(double)) + ws_align(sizeof(int));
+}
+inline Workspace ws_carve(void *base, int max_chunks, int ne) {
+    Workspace w;
+    char *p = (char *)base;
+    w.part = (double *)p;    p += ws_align((size_t)max_chunks * NSTAT_MAX * sizeof(double));
+    w.flag = (uint32_t *)p;  p += ws_align((size_t)max_chunks * CHUNK * sizeof(uint32_t));
+    w.nflag = (int32_t *)p;  p += ws_align((size_t)max_chunks * sizeof(int32_t));
+    w.foff = (int32_t *)p;   p += ws_align((size_t)(max_chunks + 1) * sizeof(int32_t));
+    w.ydd = (double *)p;     p += ws_align((size_t)ne * max_chunks * CHUNK * sizeof(double));
+    w.work = (int *)p;
+    w.max_chunks = max_chunks;
+    w.ydd_ne = ne;
+    return w;
+}
+
 struct GraphSlot {
     bool built = false;
     int n = 0, M = 0, ne = 0, ncls = 0;
@@ -78,18 +116,15 @@ struct amm_ctx {
     std::vector<amm::GraphSlot> slots;
     hipStream_t last_stream = nullptr;
     double *d_acc = nullptr;            // [graphs * NSTAT_MAX]
-    double *d_part = nullptr;           // chunk partials [MAX_CHUNKS * NSTAT_MAX]
-    uint32_t *d_flag = nullptr;         // flagged offsets [MAX_CHUNKS * CHUNK]
-    int32_t *d_nflag = nullptr;         // per chunk
-    int32_t *d_foff = nullptr;          // exclusive scan of d_nflag [MAX_CHUNKS + 1]
-    double *d_ydd = nullptr;            // DD results of flagged points, [ne][MAX_GROUP_CHUNKS * CHUNK]
-    int ydd_ne = 0;
+    amm::Workspace own;                 // allocated by the context (groups of MAX_GROUP_CHUNKS), on first use
+    amm::Workspace user;                // carved from amm_set_workspace memory (caller-owned)
+    bool use_user_ws = false;
+    const amm::Workspace &ws() const { return use_user_ws ? user : own; }
     void *d_segs = nullptr;             // segment tables of one call (SegDev), device
     void *h_segs = nullptr;             // pinned staging copy
     size_t seg_cap = 0;                 // capacity in segments
     hipEvent_t seg_ev = nullptr;        // recorded after the last staging copy
     hipEvent_t run_ev = nullptr;        // recorded after the last kernel of a run (on its stream)
-    int *d_work = nullptr;              // work counter of the persistent fused kernel
     uint64_t *d_base = nullptr;         // sample base added by replays of a captured batch
     hipStream_t cap_stream = nullptr;   // internal stream for graph capture and replay
     int generator = 0;                  // 0 Philox4x32-10, 1 MRG32k3a (AMM_OPT_GENERATOR)

@@ -1,13 +1,16 @@
 // amm_device.hip -- HIP kernels for gfx950 and the C ABI of libamm.
 //
-// Kernels (one thread = one sample, 256-thread blocks = 4 wave64):
-//   k_sample     Philox -> density sample (Sec. III.A) -> z, g = x 2^j
+// Kernels (one thread = one sample, 128-thread blocks = 2 wave64; the Monte
+// Carlo kernels are in amm_kernels.h):
+//   k_sample     Philox4x32-10 or MRG32k3a -> density sample (Sec. III.A) -> z, g = x 2^j
 //   k_eval       forest-subtracted integrands of all insertions at given z
-//   k_integrate  sample + evaluate + round-off check (eq. interval_accept) +
+//   k_integrate / k_integrate_fused
+//                sample + evaluate + round-off check (eq. interval_accept) +
 //                per-chunk deterministic partial sums; flagged samples are
 //                compacted per chunk in sample order
-//   k_dd         double-double recompute of the flagged samples of a chunk
-//   k_reduce     fixed-order sum of chunk partials into graph accumulators
+//   k_flag_scan, k_dd_points, k_dd_reduce
+//                double-double recompute of the flagged samples of a group
+//   k_reduce_seg fixed-order sum of chunk partials into graph accumulators
 // Sums are reduced in a fixed tree keyed by chunk, so results do not depend on
 // the grid size.
 #include <hip/hip_runtime.h>
@@ -17,6 +20,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <algorithm>
 #include <thread>
 #include <type_traits>
 #include <string>
@@ -49,8 +53,9 @@ amm_ctx::~amm_ctx() {
         hipFree(s.d_deg1); hipFree(s.d_deg3); hipFree(s.d_W1); hipFree(s.d_logdeg1);
         hipFree(s.d_ptheta); hipFree(s.d_pilotW);
     }
-    hipFree(d_acc); hipFree(d_part); hipFree(d_flag); hipFree(d_nflag); hipFree(d_foff); hipFree(d_ydd);
-    hipFree(d_segs); hipFree(d_work); hipFree(d_base); hipFree(d_mrg_tab);
+    hipFree(d_acc);
+    hipFree(own.part); hipFree(own.flag); hipFree(own.nflag); hipFree(own.foff); hipFree(own.ydd); hipFree(own.work);
+    hipFree(d_segs); hipFree(d_base); hipFree(d_mrg_tab);
     if (seg_ev) hipEventSynchronize(seg_ev), hipEventDestroy(seg_ev);
     if (cap_stream) hipStreamSynchronize(cap_stream), hipStreamDestroy(cap_stream);
     hipHostFree(h_segs);
@@ -218,10 +223,11 @@ constexpr int DD_GRID = 4096;                 // blocks of the per-point DD reco
 
 // FP64 pass of one segment into the group buffers at its chunk offset.
 template <int N>
-void launch_seg_fp64(const GraphSlot &gs, const SegDev &S, int grid, amm_ctx *c, hipStream_t s, bool use_gen) {
-    double *part = c->d_part + (size_t)S.gchunk * NSTAT_MAX;
-    uint32_t *flag = c->d_flag + (size_t)S.gchunk * CHUNK;
-    int32_t *nflag = c->d_nflag + S.gchunk;
+void launch_seg_fp64(const GraphSlot &gs, const SegDev &S, int grid, const Workspace &ws, hipStream_t s,
+                     bool use_gen) {
+    double *part = ws.part + (size_t)S.gchunk * NSTAT_MAX;
+    uint32_t *flag = ws.flag + (size_t)S.gchunk * CHUNK;
+    int32_t *nflag = ws.nflag + S.gchunk;
     if (use_gen && gen_launch(N, S.g))
         gen_launch(N, S.g)(GEN_RUN, &S.D, &S.A, grid, nullptr, 0, nullptr, nullptr, nullptr, s, part, flag, nflag);
     else
@@ -230,12 +236,34 @@ void launch_seg_fp64(const GraphSlot &gs, const SegDev &S, int grid, amm_ctx *c,
 
 // DD pass and reduction of one group (segments [k0, k1) of the staged table).
 template <int N>
-void launch_group_tail(amm_ctx *c, const SegDev *d_segs, int nseg, int nch, int grid_red, hipStream_t s,
-                       amm_ctx::Ev *ev) {
-    launch_dd_group<N>(d_segs, nseg, nch, DD_GRID, grid_red, c->d_part, c->d_flag, c->d_nflag, c->d_foff, c->d_ydd,
-                       (size_t)MAX_GROUP_CHUNKS * CHUNK, s);
+void launch_group_tail(amm_ctx *c, const Workspace &ws, const SegDev *d_segs, int nseg, int nch, int grid_red,
+                       hipStream_t s, amm_ctx::Ev *ev) {
+    launch_dd_group<N>(d_segs, nseg, nch, DD_GRID, grid_red, ws.part, ws.flag, ws.nflag, ws.foff, ws.ydd,
+                       ws.ydd_cap(), s);
     if (ev) hipEventRecord(ev->c, s);
-    hipLaunchKernelGGL(k_reduce_seg, dim3(NSTAT_MAX, nseg), dim3(256), 0, s, d_segs, c->d_part, c->d_acc);
+    hipLaunchKernelGGL(k_reduce_seg, dim3(NSTAT_MAX, nseg), dim3(256), 0, s, d_segs, ws.part, c->d_acc);
+}
+
+// The context's own workspace (groups of MAX_GROUP_CHUNKS chunks), allocated
+// on first use; the double-double region grows to ne insertions.
+int ensure_own_ws(amm_ctx *c, int ne) {
+    Workspace &w = c->own;
+    if (!w.part) {
+        w.max_chunks = MAX_GROUP_CHUNKS;
+        HIPCHK(hipMalloc((void **)&w.part, (size_t)MAX_GROUP_CHUNKS * NSTAT_MAX * sizeof(double)));
+        HIPCHK(hipMalloc((void **)&w.flag, (size_t)MAX_GROUP_CHUNKS * CHUNK * sizeof(uint32_t)));
+        HIPCHK(hipMalloc((void **)&w.nflag, (size_t)MAX_GROUP_CHUNKS * sizeof(int32_t)));
+        HIPCHK(hipMalloc((void **)&w.foff, (size_t)(MAX_GROUP_CHUNKS + 1) * sizeof(int32_t)));
+        HIPCHK(hipMalloc((void **)&w.work, sizeof(int)));
+    }
+    if (w.ydd_ne < ne) {
+        HIPCHK(hipFree(w.ydd));
+        w.ydd = nullptr;
+        w.ydd_ne = 0;
+        HIPCHK(hipMalloc((void **)&w.ydd, (size_t)ne * MAX_GROUP_CHUNKS * CHUNK * sizeof(double)));
+        w.ydd_ne = ne;
+    }
+    return AMM_OK;
 }
 
 void prof_collect(amm_ctx *c) {
@@ -270,13 +298,8 @@ int amm_create(amm_ctx **out, int device) {
     HIPCHK(hipSetDevice(device));
     std::unique_ptr<amm_ctx> c(new amm_ctx);
     c->device = device;
-    HIPCHK(hipMalloc((void **)&c->d_part, (size_t)MAX_GROUP_CHUNKS * NSTAT_MAX * sizeof(double)));
-    HIPCHK(hipMalloc((void **)&c->d_flag, (size_t)MAX_GROUP_CHUNKS * CHUNK * sizeof(uint32_t)));
-    HIPCHK(hipMalloc((void **)&c->d_nflag, (size_t)MAX_GROUP_CHUNKS * sizeof(int32_t)));
-    HIPCHK(hipMalloc((void **)&c->d_foff, (size_t)(MAX_GROUP_CHUNKS + 1) * sizeof(int32_t)));
     HIPCHK(hipEventCreateWithFlags(&c->seg_ev, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->run_ev, hipEventDisableTiming));
-    HIPCHK(hipMalloc((void **)&c->d_work, sizeof(int)));
     HIPCHK(hipMalloc((void **)&c->d_base, sizeof(uint64_t)));
     for (int i = 0; i < amm_ctx::NSIDE; ++i) {
         HIPCHK(hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
@@ -462,11 +485,8 @@ int amm_eval(amm_ctx *c, int g, const double *z, uint64_t n, double *I, double *
     return AMM_OK;
 }
 
-// Validates a run, prepares the group buffers and stages the segment table of
-// the run on `st` (base_dev: optional device word added to every sample index).
-static int prepare_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, const uint64_t *base_dev,
-                       std::vector<SegDev> &segs, std::vector<int> &group_begin,
-                       const uint64_t *c0_per_graph = nullptr, const uint64_t *n_per_graph_arr = nullptr) {
+// Checks a run's parameters against the context.
+static int check_run(amm_ctx *c, const amm_run_params *r) {
     if (!c || !r) return fail(AMM_E_ARG, "amm_integrate: bad argument");
     if (r->graph_begin < 0 || r->graph_end > (int)c->slots.size() || r->graph_begin >= r->graph_end)
         return fail(AMM_E_ARG, "amm_integrate: bad graph range");
@@ -476,43 +496,59 @@ static int prepare_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, cons
     if (c->loops == 1 && r->force_flag)
         return fail(AMM_E_ARG, "amm_integrate: double-double recompute is disabled at 1 loop (force_flag)");
     if (r->blocks_per_cu < 0 || r->blocks_per_cu > 64) return fail(AMM_E_ARG, "amm_integrate: blocks_per_cu 0..64");
-    HIPCHK(hipSetDevice(c->device));
-    const int ne_ctx = 2 * c->loops - 1;
-    if (c->ydd_ne < ne_ctx) {                 // DD results of up to one group of samples
-        HIPCHK(hipFree(c->d_ydd));
-        c->d_ydd = nullptr;
-        c->ydd_ne = 0;
-        HIPCHK(hipMalloc((void **)&c->d_ydd, (size_t)ne_ctx * MAX_GROUP_CHUNKS * CHUNK * sizeof(double)));
-        c->ydd_ne = ne_ctx;
+    return AMM_OK;
+}
+
+// Number of segments a run is cut into with groups of max_chunks chunks.
+static size_t count_segments(const amm_run_params *r, int max_chunks, const uint64_t *n_per_graph_arr) {
+    size_t n = 0;
+    for (int g = r->graph_begin; g < r->graph_end; ++g) {
+        const uint64_t ng = n_per_graph_arr ? n_per_graph_arr[g - r->graph_begin] : r->n_per_graph;
+        const uint64_t nch = (ng + CHUNK - 1) / CHUNK;
+        n += (size_t)((nch + max_chunks - 1) / max_chunks);
     }
+    return n;
+}
+
+// Segments: each graph's chunk range cut into pieces of at most max_chunks
+// chunks; groups: consecutive segments of distinct graphs, at most
+// max_chunks chunks in all.  Writes the segments to out (room for cap) and the
+// first segment of every group, then the segment count, to gbeg (room for
+// cap + 1).  Allocates nothing.
+static int plan_segments(amm_ctx *c, const amm_run_params *r, const uint64_t *base_dev, int max_chunks,
+                         const uint64_t *c0_per_graph, const uint64_t *n_per_graph_arr, SegDev *out, size_t cap,
+                         int *gbeg, int *nseg_out, int *ngroups_out) {
     // graph order inside groups: heaviest plan first (cost grouping) or natural
-    std::vector<int> order;
-    for (int g = r->graph_begin; g < r->graph_end; ++g) order.push_back(g);
+    int order[1024];
+    const int G = r->graph_end - r->graph_begin;
+    if (G > 1024) return fail(AMM_E_TOOBIG, "amm_integrate: more than 1024 graphs in one run");
+    for (int k = 0; k < G; ++k) order[k] = r->graph_begin + k;
     if (c->order_by_cost)
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-            return c->slots[a].plan.flops_per_sample > c->slots[b].plan.flops_per_sample;
+        std::sort(order, order + G, [&](int a, int b) {
+            const double fa = c->slots[a].plan.flops_per_sample, fb = c->slots[b].plan.flops_per_sample;
+            return fa > fb || (fa == fb && a < b);
         });
-    // Segments: each graph's chunk range cut into pieces of at most one group;
-    // groups: consecutive segments of distinct graphs, at most MAX_GROUP_CHUNKS.
-    segs.clear();
-    group_begin.clear();
-    int gch = MAX_GROUP_CHUNKS, last_g = -1;
-    for (int g : order) {
+    size_t nseg = 0;
+    int ngroups = 0;
+    int gch = max_chunks, last_g = -1;
+    for (int k = 0; k < G; ++k) {
+        const int g = order[k];
         GraphSlot &s = c->slots[g];
         bool learned = r->sampler == 1 && s.d_ptheta != nullptr;
-        const int k = g - r->graph_begin;
-        const uint64_t c0 = c0_per_graph ? c0_per_graph[k] : r->counter0;
-        const uint64_t ng = n_per_graph_arr ? n_per_graph_arr[k] : r->n_per_graph;
+        const int kk = g - r->graph_begin;
+        const uint64_t c0 = c0_per_graph ? c0_per_graph[kk] : r->counter0;
+        const uint64_t ng = n_per_graph_arr ? n_per_graph_arr[kk] : r->n_per_graph;
         const uint64_t nchunks_total = (ng + CHUNK - 1) / CHUNK;
         if (c0 + ng < c0 || !mrg_range_ok(c, c0 + ng))
             return fail(AMM_E_ARG, "amm_integrate: MRG32k3a sample indices >= 2^44");
-        for (uint64_t ch0 = 0; ch0 < nchunks_total; ch0 += MAX_GROUP_CHUNKS) {
-            int nch = (int)std::min<uint64_t>(MAX_GROUP_CHUNKS, nchunks_total - ch0);
-            if (gch + nch > MAX_GROUP_CHUNKS || last_g == g) {
-                group_begin.push_back((int)segs.size());
+        for (uint64_t ch0 = 0; ch0 < nchunks_total; ch0 += max_chunks) {
+            int nch = (int)std::min<uint64_t>(max_chunks, nchunks_total - ch0);
+            if (nseg >= cap) return fail(AMM_E_TOOBIG, "amm_integrate: run needs more segments than the table holds");
+            if (gch + nch > max_chunks || last_g == g) {
+                gbeg[ngroups++] = (int)nseg;
                 gch = 0;
             }
-            SegDev S;
+            SegDev &S = out[nseg];
             std::memset(&S, 0, sizeof(S));
             S.A.seed = r->seed;
             S.A.begin = c0;
@@ -533,15 +569,40 @@ static int prepare_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, cons
             S.g = g;
             S.nst = s.nstat();
             S.gchunk = gch;
-            segs.push_back(S);
+            ++nseg;
             gch += nch;
             last_g = g;
         }
     }
-    group_begin.push_back((int)segs.size());
-    // The segment table, chunk partials, flags and recompute buffers are the
-    // context's: a run enqueued on another stream than the previous one waits
-    // for that run's last kernel before it restages or overwrites them.
+    gbeg[ngroups] = (int)nseg;
+    *nseg_out = (int)nseg;
+    *ngroups_out = ngroups;
+    return AMM_OK;
+}
+
+// Validates a run, prepares the group buffers and stages the segment table of
+// the run on `st` (base_dev: optional device word added to every sample index).
+static int prepare_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, const uint64_t *base_dev,
+                       std::vector<SegDev> &segs, std::vector<int> &group_begin,
+                       const uint64_t *c0_per_graph = nullptr, const uint64_t *n_per_graph_arr = nullptr) {
+    if (int rc = check_run(c, r)) return rc;
+    HIPCHK(hipSetDevice(c->device));
+    const int ne_ctx = 2 * c->loops - 1;
+    if (!c->use_user_ws)
+        if (int rc = ensure_own_ws(c, ne_ctx)) return rc;
+    const Workspace &ws = c->ws();
+    const size_t nmax = count_segments(r, ws.max_chunks, n_per_graph_arr);
+    segs.resize(nmax);
+    group_begin.resize(nmax + 1);
+    int nseg = 0, ngroups = 0;
+    if (int rc = plan_segments(c, r, base_dev, ws.max_chunks, c0_per_graph, n_per_graph_arr, segs.data(), nmax,
+                               group_begin.data(), &nseg, &ngroups))
+        return rc;
+    segs.resize(nseg);
+    group_begin.resize(ngroups + 1);
+    // The segment table and the workspace are shared by the context's runs: a
+    // run enqueued on another stream than the previous one waits for that
+    // run's last kernel before it restages or overwrites them.
     HIPCHK(hipStreamWaitEvent(st, c->run_ev, 0));
     // stage the table: wait until the previous call's copy has been consumed
     HIPCHK(hipEventSynchronize(c->seg_ev));
@@ -562,7 +623,7 @@ static int prepare_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, cons
 }
 
 // Whether a group's FP64 pass runs as one persistent interpreter launch.
-static bool group_fused(const amm_ctx *c, const std::vector<SegDev> &segs, int k0, int k1) {
+static bool group_fused(const amm_ctx *c, const SegDev *segs, int k0, int k1) {
     if (!c->use_fused) return false;
     for (int k = k0; k < k1; ++k)
         if (c->use_gen && gen_launch(c->loops, segs[k].g)) return false;
@@ -570,15 +631,15 @@ static bool group_fused(const amm_ctx *c, const std::vector<SegDev> &segs, int k
 }
 
 // Enqueues the kernels of every group of a prepared run on `st` (also used
-// under stream capture; then `prof` must be false).
-static void enqueue_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, const std::vector<SegDev> &segs,
-                        const std::vector<int> &group_begin, bool prof) {
+// under stream capture; then `prof` must be false).  segs: the host copy of the
+// staged table d_segs; group_begin: ngroups + 1 segment indices.
+static void enqueue_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, const SegDev *segs,
+                        const int *group_begin, int ngroups, const SegDev *d_segs, const Workspace &ws, bool prof) {
     int dev_cus = 256;
     hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device);
-    const SegDev *d_segs = (const SegDev *)c->d_segs;
     const int bpc = r->blocks_per_cu > 0 ? r->blocks_per_cu : (c->blocks_per_cu > 0 ? c->blocks_per_cu : 8);
     const int grid_target = bpc * dev_cus;
-    for (size_t q = 0; q + 1 < group_begin.size(); ++q) {
+    for (int q = 0; q < ngroups; ++q) {
         const int k0 = group_begin[q], k1 = group_begin[q + 1];
         const int nch = segs[k1 - 1].gchunk + segs[k1 - 1].A.nchunks;
         amm_ctx::Ev ev, *evp = nullptr;
@@ -597,12 +658,12 @@ static void enqueue_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, con
         }
         if (group_fused(c, segs, k0, k1)) {
             const int grid = std::min(nch, grid_target);
-            hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, c->d_work, 0);
+            hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.work, 0);
             switch (c->loops) {
-                case 1: hipLaunchKernelGGL(k_integrate_fused<1>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, c->d_work, c->d_part, c->d_flag, c->d_nflag); break;
-                case 2: hipLaunchKernelGGL(k_integrate_fused<2>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, c->d_work, c->d_part, c->d_flag, c->d_nflag); break;
-                case 3: hipLaunchKernelGGL(k_integrate_fused<3>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, c->d_work, c->d_part, c->d_flag, c->d_nflag); break;
-                case 4: hipLaunchKernelGGL(k_integrate_fused<4>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, c->d_work, c->d_part, c->d_flag, c->d_nflag); break;
+                case 1: hipLaunchKernelGGL(k_integrate_fused<1>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
+                case 2: hipLaunchKernelGGL(k_integrate_fused<2>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
+                case 3: hipLaunchKernelGGL(k_integrate_fused<3>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
+                case 4: hipLaunchKernelGGL(k_integrate_fused<4>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
             }
         } else {
             // one launch per segment; they write disjoint chunks, so they run
@@ -621,10 +682,10 @@ static void enqueue_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, con
                 load[li] += c->slots[segs[k].g].plan.flops_per_sample * (double)segs[k].A.nchunks;
                 hipStream_t ls = ns > 1 ? c->side[li] : st;
                 switch (c->loops) {
-                    case 1: launch_seg_fp64<1>(c->slots[segs[k].g], segs[k], grid, c, ls, c->use_gen); break;
-                    case 2: launch_seg_fp64<2>(c->slots[segs[k].g], segs[k], grid, c, ls, c->use_gen); break;
-                    case 3: launch_seg_fp64<3>(c->slots[segs[k].g], segs[k], grid, c, ls, c->use_gen); break;
-                    case 4: launch_seg_fp64<4>(c->slots[segs[k].g], segs[k], grid, c, ls, c->use_gen); break;
+                    case 1: launch_seg_fp64<1>(c->slots[segs[k].g], segs[k], grid, ws, ls, c->use_gen); break;
+                    case 2: launch_seg_fp64<2>(c->slots[segs[k].g], segs[k], grid, ws, ls, c->use_gen); break;
+                    case 3: launch_seg_fp64<3>(c->slots[segs[k].g], segs[k], grid, ws, ls, c->use_gen); break;
+                    case 4: launch_seg_fp64<4>(c->slots[segs[k].g], segs[k], grid, ws, ls, c->use_gen); break;
                 }
             }
             if (ns > 1)
@@ -636,10 +697,10 @@ static void enqueue_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, con
         if (evp) hipEventRecord(ev.b, st);
         const int grid_red = std::min(nch, grid_target);
         switch (c->loops) {
-            case 1: launch_group_tail<1>(c, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
-            case 2: launch_group_tail<2>(c, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
-            case 3: launch_group_tail<3>(c, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
-            case 4: launch_group_tail<4>(c, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
+            case 1: launch_group_tail<1>(c, ws, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
+            case 2: launch_group_tail<2>(c, ws, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
+            case 3: launch_group_tail<3>(c, ws, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
+            case 4: launch_group_tail<4>(c, ws, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
         }
         if (evp) {
             hipEventRecord(ev.d, st);
@@ -654,6 +715,38 @@ static void zero_acc(amm_ctx *c, const amm_run_params *r, hipStream_t st) {
             hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, c->d_acc + (size_t)g * NSTAT_MAX, NSTAT_MAX);
 }
 
+size_t amm_workspace_bytes(int chunks_per_group) {
+    if (chunks_per_group < 1 || chunks_per_group > MAX_GROUP_CHUNKS) return 0;
+    return ws_bytes(chunks_per_group, MAXNE);
+}
+
+int amm_set_workspace(amm_ctx *c, void *dev_ptr, size_t bytes) {
+    if (!c) return fail(AMM_E_ARG, "amm_set_workspace: ctx is NULL");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipEventSynchronize(c->run_ev));   // no enqueued run still uses the current workspace
+    if (!dev_ptr) {
+        c->use_user_ws = false;
+        c->user = Workspace();
+        return AMM_OK;
+    }
+    if ((uintptr_t)dev_ptr % 256 != 0) return fail(AMM_E_ARG, "amm_set_workspace: pointer not 256-byte aligned");
+    int lo = 0, hi = MAX_GROUP_CHUNKS;        // largest chunk count whose workspace fits
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        if (ws_bytes(mid, MAXNE) <= bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    if (lo < 1) return fail(AMM_E_ARG, "amm_set_workspace: smaller than amm_workspace_bytes(1)");
+    c->user = ws_carve(dev_ptr, lo, MAXNE);
+    c->use_user_ws = true;
+    // the context's own group buffers are not used while a workspace is set
+    Workspace &w = c->own;
+    HIPCHK(hipFree(w.part)); HIPCHK(hipFree(w.flag)); HIPCHK(hipFree(w.nflag)); HIPCHK(hipFree(w.foff));
+    HIPCHK(hipFree(w.ydd)); HIPCHK(hipFree(w.work));
+    w = Workspace();
+    return AMM_OK;
+}
+
 int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     std::vector<SegDev> segs;
@@ -661,7 +754,8 @@ int amm_integrate(amm_ctx *c, const amm_run_params *r, void *stream) {
     int rc = prepare_run(c, r, st, nullptr, segs, group_begin);
     if (rc) return rc;
     zero_acc(c, r, st);
-    enqueue_run(c, r, st, segs, group_begin, c->prof);
+    enqueue_run(c, r, st, segs.data(), group_begin.data(), (int)group_begin.size() - 1, (const SegDev *)c->d_segs, c->ws(),
+                c->prof);
     HIPCHK(hipEventRecord(c->run_ev, st));
     HIPCHK(hipGetLastError());
     c->last_stream = st;
@@ -692,7 +786,8 @@ int amm_integrate_batches(amm_ctx *c, const amm_run_params *r, uint64_t n_batche
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    enqueue_run(c, r, cs, segs, group_begin, false);
+    enqueue_run(c, r, cs, segs.data(), group_begin.data(), (int)group_begin.size() - 1, (const SegDev *)c->d_segs, c->ws(),
+                false);
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, cs, c->d_base, r->n_per_graph);
     hipError_t ce = hipStreamEndCapture(cs, &graph);
     if (ce != hipSuccess) {
@@ -882,7 +977,8 @@ int amm_integrate_adaptive(amm_ctx *c, const amm_run_params *r, uint64_t budget_
         int rc = prepare_run(c, &q, st, nullptr, segs, group_begin, c0.data(), nr.data());
         if (rc) return rc;
         zero_acc(c, &q, st);
-        enqueue_run(c, &q, st, segs, group_begin, c->prof);
+        enqueue_run(c, &q, st, segs.data(), group_begin.data(), (int)group_begin.size() - 1, (const SegDev *)c->d_segs,
+                    c->ws(), c->prof);
         HIPCHK(hipEventRecord(c->run_ev, st));
         HIPCHK(hipGetLastError());
         c->last_stream = st;

@@ -36,6 +36,36 @@ def _tau(amm, n_run, n_pilot=30_000):
     return amm.accept_thresholds(n_run)
 
 
+def test_caller_workspace(amm):
+    """amm_set_workspace: a torch-owned workspace of 300 chunks per group gives
+    the own-buffer run's counters exactly and its sums to rounding (segment sums
+    added in another order); back on the own buffers the run is bit-identical."""
+    amm.enumerate(2)
+    amm.build_tables()
+    N = 700_001
+    tau = _tau(amm, N)
+    amm.integrate(seed=6, n_per_graph=N, accept_tau=tau)
+    a = _acc(amm)
+    nbytes = amm.workspace_bytes(300)
+    assert nbytes > 0 and amm.workspace_bytes(0) == 0 and amm.workspace_bytes(32769) == 0
+    ws = torch.empty(nbytes, dtype=torch.uint8, device='cuda')
+    try:
+        amm.set_workspace(ws)
+        amm.integrate(seed=6, n_per_graph=N, accept_tau=tau)
+        b = _acc(amm)
+    finally:
+        amm.set_workspace(None)
+    for x, y in zip(a, b):
+        assert x['n'] == y['n'] and x['n_flag'] == y['n_flag'] and x['n_dd_fail'] == y['n_dd_fail']
+        assert abs(x['sum_y'] - y['sum_y']) <= 1e-12 * y['sum_abs']
+    assert sum(x['n_flag'] for x in a) > 0
+    amm.integrate(seed=6, n_per_graph=N, accept_tau=tau)
+    _same(a, _acc(amm))
+    from paper_1909_08015_amd.amm import AmmError
+    with pytest.raises(AmmError):
+        amm.set_workspace(ws[: amm.workspace_bytes(1) - 256])
+
+
 def test_fused_launch_matches_per_graph_launches(amm):
     from paper_1909_08015_amd.amm import OPT_GENERATED, OPT_FUSED, OPT_ORDER_BY_COST
     amm.enumerate(3)
