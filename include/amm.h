@@ -286,6 +286,21 @@ int amm_combine(int n, const double *mean1, const double *sigma1, const double *
  * graph_begin doubles to the host array tau (to pass as accept_tau). */
 int amm_accept_thresholds(amm_ctx *ctx, int graph_begin, int graph_end, uint64_t n_run, double *tau);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the run of
+ * amm_integrate with every buffer it needs beyond the context's tables and
+ * accumulators taken from a static device array of the library (20.4 MB
+ * per device, held from the first amm_create on that device until the process
+ * ends).  Calls no hipMalloc, hipFree or other allocating routine.  Groups
+ * hold 256 chunks (262144 samples); a run may have at most 1024 segments,
+ * i.e. sum over its graphs of ceil(n_per_graph / 262144) <= 1024, else
+ * AMM_E_TOOBIG.  Results equal amm_integrate's up to the order in which
+ * segment sums are added (counters exactly).  Every call on a device shares
+ * that device's array: calls that overlap on one device (other contexts, or
+ * other streams without ordering) race.  Errors: as amm_integrate, and
+ * AMM_E_TOOBIG. */
+int amm_integrate_static(amm_ctx *ctx, const amm_run_params *run, void *stream);
+
 /* Read accumulators (synchronises the last stream used).  g >= 0 selects a
  * graph; e >= 0 an insertion of it, e = -1 the sum over its insertions.
  * cls_k >= 0 with g = -1 selects a class (k, m, m') summed over all built

@@ -86,6 +86,7 @@ SYMBOLS = {
     'amm_set_sector_table': (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     'amm_set_workspace': (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     'amm_workspace_bytes': (C.c_size_t, [C.c_int]),
+    'amm_integrate_static': (C.c_int, [C.c_void_p, C.POINTER(RunParams), C.c_void_p]),
 }
 
 
@@ -237,6 +238,13 @@ class Context:
         rp, _keep = self._run_params(seed, n_per_graph, graph_begin, graph_end, counter0, sampler, force_flag,
                                      blocks_per_cu, accumulate, accept_tau)
         _check(lib().amm_integrate(self.h, C.byref(rp), _stream(stream)), 'amm_integrate')
+
+    def integrate_static(self, seed, n_per_graph, graph_begin=0, graph_end=None, counter0=0, sampler=0,
+                         force_flag=0, blocks_per_cu=0, accumulate=0, accept_tau=None, stream=None):
+        """amm_integrate with the library's static device scratch (no allocation)."""
+        rp, _keep = self._run_params(seed, n_per_graph, graph_begin, graph_end, counter0, sampler, force_flag,
+                                     blocks_per_cu, accumulate, accept_tau)
+        _check(lib().amm_integrate_static(self.h, C.byref(rp), _stream(stream)), 'amm_integrate_static')
 
     def set_workspace(self, tensor=None):
         """Caller-owned device workspace (a torch tensor kept alive by the

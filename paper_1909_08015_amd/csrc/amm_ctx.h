@@ -120,6 +120,9 @@ struct amm_ctx {
     amm::Workspace user;                // carved from amm_set_workspace memory (caller-owned)
     bool use_user_ws = false;
     const amm::Workspace &ws() const { return use_user_ws ? user : own; }
+    void *static_base = nullptr;        // this device's static scratch (amm_integrate_static)
+    hipEvent_t static_seg_ev = nullptr; // recorded after the last staging copy of the static path
+    void *static_stage = nullptr;       // host staging of the static path's segment table (SegDev[])
     void *d_segs = nullptr;             // segment tables of one call (SegDev), device
     void *h_segs = nullptr;             // pinned staging copy
     size_t seg_cap = 0;                 // capacity in segments

@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <algorithm>
 #include <thread>
 #include <type_traits>
@@ -57,6 +58,8 @@ amm_ctx::~amm_ctx() {
     hipFree(own.part); hipFree(own.flag); hipFree(own.nflag); hipFree(own.foff); hipFree(own.ydd); hipFree(own.work);
     hipFree(d_segs); hipFree(d_base); hipFree(d_mrg_tab);
     if (seg_ev) hipEventSynchronize(seg_ev), hipEventDestroy(seg_ev);
+    if (static_seg_ev) hipEventSynchronize(static_seg_ev), hipEventDestroy(static_seg_ev);
+    delete[] (SegDev *)static_stage;
     if (cap_stream) hipStreamSynchronize(cap_stream), hipStreamDestroy(cap_stream);
     hipHostFree(h_segs);
     mlp_free(mlp);
@@ -266,6 +269,46 @@ int ensure_own_ws(amm_ctx *c, int ne) {
     return AMM_OK;
 }
 
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Static scratch of amm_integrate_static: the workspace for groups of
+// STATIC_GROUP_CHUNKS chunks (any loop order), then a segment table of
+// STATIC_MAX_SEGS entries.  One copy per device, held while the process
+// lives; host code reaches it only through the address hipGetSymbolAddress
+// returns for the device (static_setup).
+// ---------------------------------------------------------------------------
+constexpr int STATIC_GROUP_CHUNKS = 256;      // 262144 samples per group
+constexpr int STATIC_MAX_SEGS = 1024;
+constexpr size_t STATIC_WS_BYTES = ws_bytes(STATIC_GROUP_CHUNKS, MAXNE);
+constexpr size_t STATIC_BYTES = STATIC_WS_BYTES + ws_align(STATIC_MAX_SEGS * sizeof(SegDev));
+static __device__ __align__(256) unsigned char scratch[STATIC_BYTES];
+
+namespace {
+
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[STATIC_MAX_DEVICES] = {};
+
+// Once per device (with the device current): the device address of `scratch`.
+// Also the context's staging table and event of the static path.
+int static_setup(amm_ctx *c) {
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (c->device >= STATIC_MAX_DEVICES) return fail(AMM_E_ARG, "amm_create: device index beyond 63");
+        if (!g_static_ptr[c->device]) {
+            void *ptr = nullptr;
+            HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr) return fail(AMM_E_HIP, "amm_create: no device address for the static scratch");
+            g_static_ptr[c->device] = ptr;
+        }
+        c->static_base = g_static_ptr[c->device];
+    }
+    HIPCHK(hipEventCreateWithFlags(&c->static_seg_ev, hipEventDisableTiming));
+    c->static_stage = new SegDev[STATIC_MAX_SEGS];
+    return AMM_OK;
+}
+
 void prof_collect(amm_ctx *c) {
     for (auto &e : c->evs) {
         hipEventSynchronize(e.d);
@@ -301,6 +344,7 @@ int amm_create(amm_ctx **out, int device) {
     HIPCHK(hipEventCreateWithFlags(&c->seg_ev, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->run_ev, hipEventDisableTiming));
     HIPCHK(hipMalloc((void **)&c->d_base, sizeof(uint64_t)));
+    if (int rc = static_setup(c.get())) return rc;
     for (int i = 0; i < amm_ctx::NSIDE; ++i) {
         HIPCHK(hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming));
@@ -713,6 +757,36 @@ static void zero_acc(amm_ctx *c, const amm_run_params *r, hipStream_t st) {
     if (!r->accumulate)
         for (int g = r->graph_begin; g < r->graph_end; ++g)
             hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, c->d_acc + (size_t)g * NSTAT_MAX, NSTAT_MAX);
+}
+
+int amm_integrate_static(amm_ctx *c, const amm_run_params *r, void *stream) {
+    if (int rc = check_run(c, r)) return rc;
+    if (!c->static_base || !c->static_stage) return fail(AMM_E_ARG, "amm_integrate_static: no static scratch");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(c->device));
+    if (count_segments(r, STATIC_GROUP_CHUNKS, nullptr) > (size_t)STATIC_MAX_SEGS)
+        return fail(AMM_E_TOOBIG, "amm_integrate_static: the run needs more than 1024 segments of 262144 samples "
+                                  "(sum over graphs of ceil(n_per_graph / 262144))");
+    const Workspace ws = ws_carve(c->static_base, STATIC_GROUP_CHUNKS, MAXNE);
+    SegDev *d_segs = (SegDev *)((char *)c->static_base + STATIC_WS_BYTES);
+    SegDev *h = (SegDev *)c->static_stage;
+    int gbeg[STATIC_MAX_SEGS + 1];
+    // the previous static call's staging copy has left the host table
+    HIPCHK(hipEventSynchronize(c->static_seg_ev));
+    int nseg = 0, ngroups = 0;
+    if (int rc = plan_segments(c, r, nullptr, STATIC_GROUP_CHUNKS, nullptr, nullptr, h, STATIC_MAX_SEGS, gbeg, &nseg,
+                               &ngroups))
+        return rc;
+    // after this context's previous run (any stream), which may use the scratch
+    HIPCHK(hipStreamWaitEvent(st, c->run_ev, 0));
+    HIPCHK(hipMemcpyAsync(d_segs, h, (size_t)nseg * sizeof(SegDev), hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(c->static_seg_ev, st));
+    zero_acc(c, r, st);
+    enqueue_run(c, r, st, h, gbeg, ngroups, d_segs, ws, false);
+    HIPCHK(hipEventRecord(c->run_ev, st));
+    HIPCHK(hipGetLastError());
+    c->last_stream = st;
+    return AMM_OK;
 }
 
 size_t amm_workspace_bytes(int chunks_per_group) {
