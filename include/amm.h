@@ -121,7 +121,9 @@ int amm_graph_desc(const amm_ctx *ctx, int g, int *chords, int *classes);
 
 /* Build the per-graph density tables (Sec. III.A) and subtraction tables
  * (Sec. II forest formula) for graphs [graph_begin, graph_end) of the
- * enumerated loop order and upload them once.  params NULL = Calc 2. */
+ * enumerated loop order and upload them once.  params NULL = Calc 2.
+ * Integrand tables exist for 1-4 loops; at 5 loops only the density tables
+ * are built (AMM_OPT_PLANS = 0), else AMM_E_TOOBIG. */
 int amm_build_tables(amm_ctx *ctx, const amm_density_params *params,
                      int graph_begin, int graph_end);
 
@@ -211,12 +213,17 @@ size_t amm_workspace_bytes(int chunks_per_group);
  *   ((za >> 1) 2^21 + (zb >> 11) + 1/2) 2^-52 from outputs 2k+1, 2k+2.
  *   Sample indices must stay below 2^44 (AMM_E_ARG otherwise).  This option
  *   changes the samples, hence the results; the pilot of the learned sampler
- *   (amm_pilot) always uses Philox4x32-10. */
+ *   (amm_pilot) always uses Philox4x32-10.
+ * AMM_OPT_PLANS (default 1): amm_build_tables builds the integrand tables as
+ *   well as the density tables; 0 builds the density tables only (sampling
+ *   with amm_sample, e.g. at 5 loops, where integrand tables are not built);
+ *   amm_eval, amm_integrate* and amm_pilot then return AMM_E_NOTBUILT. */
 #define AMM_OPT_GENERATED 1
 #define AMM_OPT_FUSED 2
 #define AMM_OPT_ORDER_BY_COST 3
 #define AMM_OPT_BLOCKS_PER_CU 4
 #define AMM_OPT_GENERATOR 5
+#define AMM_OPT_PLANS 6
 int amm_set_option(amm_ctx *ctx, int option, int value);
 
 /* Launch-configuration autotuner: times the run `run` (its n_per_graph is the

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, 'libamm.so')
 
 AMM_OK = 0
-OPT_GENERATED, OPT_FUSED, OPT_ORDER_BY_COST, OPT_BLOCKS_PER_CU, OPT_GENERATOR = 1, 2, 3, 4, 5
+OPT_GENERATED, OPT_FUSED, OPT_ORDER_BY_COST, OPT_BLOCKS_PER_CU, OPT_GENERATOR, OPT_PLANS = 1, 2, 3, 4, 5, 6
 
 
 class AmmError(RuntimeError):

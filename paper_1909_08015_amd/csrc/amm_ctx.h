@@ -72,7 +72,8 @@ inline Workspace ws_carve(void *base, int max_chunks, int ne) {
 }
 
 struct GraphSlot {
-    bool built = false;
+    bool built = false;                       // density tables (sampling)
+    bool has_plan = false;                    // integrand tables (evaluation)
     int n = 0, M = 0, ne = 0, ncls = 0;
     int cls_of[MAXNE] = {0};
     int cls_kmm[MAXNE][3];
@@ -138,6 +139,7 @@ struct amm_ctx {
     hipEvent_t fork_ev = nullptr, join_ev[NSIDE] = {};
     // launch configuration (set by amm_autotune or amm_set_option)
     int use_fused = 1;                  // interpreter graphs: one persistent launch per group
+    int build_plans = 1;                // amm_build_tables builds integrand tables (AMM_OPT_PLANS)
     int order_by_cost = 1;              // segments of a group heaviest graph first
     int blocks_per_cu = 0;              // 0: default
     amm::MlpState mlp;

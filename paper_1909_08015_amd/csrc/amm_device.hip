@@ -399,7 +399,10 @@ int amm_graph_desc(const amm_ctx *c, int g, int *chords, int *classes) {
 int amm_build_tables(amm_ctx *c, const amm_density_params *params, int gb, int ge) {
     if (!c || c->loops == 0) return fail(AMM_E_ARG, "amm_build_tables: call amm_enumerate first");
     if (gb < 0 || ge > (int)c->graphs.size() || gb >= ge) return fail(AMM_E_ARG, "amm_build_tables: bad graph range");
-    if (c->loops > 4) return fail(AMM_E_TOOBIG, "amm_build_tables: integrand tables are built for 1..4 loops");
+    const bool plans = c->build_plans != 0;
+    if (c->loops > 4 && plans)
+        return fail(AMM_E_TOOBIG, "amm_build_tables: integrand tables are built for 1..4 loops "
+                                  "(density tables only: AMM_OPT_PLANS = 0)");
     amm_density_params p;
     if (params) p = *params;
     else p = amm_density_params{0.256, 0.839, 0.786, 0.2, 0.0, 0.2, {((1.0 - 0.03) - 0.01) - 0.06, 0.03, 0.01, 0.06}, 0.75, 1.0};
@@ -412,7 +415,8 @@ int amm_build_tables(amm_ctx *c, const amm_density_params *params, int gb, int g
             for (int g = next++; g < ge; g = next++) {
                 try {
                     build_density(c->graphs[g], p, c->slots[g].dens);
-                    build_plan(c->graphs[g], c->slots[g].plan);
+                    if (plans) build_plan(c->graphs[g], c->slots[g].plan);
+                    else c->slots[g].plan = PlanHost();
                 } catch (const std::exception &ex) {
                     errs[g - gb] = ex.what();
                 }
@@ -453,17 +457,21 @@ int amm_build_tables(amm_ctx *c, const amm_density_params *params, int gb, int g
         std::vector<int2> rg(s.plan.ranges.size());
         for (size_t i = 0; i < rg.size(); ++i) rg[i] = make_int2(s.plan.ranges[i].first, s.plan.ranges[i].second);
         int rc;
-        if ((rc = upload(&s.d_levels, s.plan.levels.data(), s.plan.levels.size()))) return rc;
-        if ((rc = upload(&s.d_terms, s.plan.terms.data(), s.plan.terms.size()))) return rc;
-        if ((rc = upload(&s.d_ops, s.plan.ops.data(), s.plan.ops.size()))) return rc;
-        if ((rc = upload(&s.d_monos, s.plan.monos.data(), s.plan.monos.size()))) return rc;
-        if ((rc = upload(&s.d_ranges, rg.data(), rg.size()))) return rc;
+        s.d_levels = nullptr; s.d_terms = nullptr; s.d_ops = nullptr; s.d_monos = nullptr; s.d_ranges = nullptr;
+        if (plans) {
+            if ((rc = upload(&s.d_levels, s.plan.levels.data(), s.plan.levels.size()))) return rc;
+            if ((rc = upload(&s.d_terms, s.plan.terms.data(), s.plan.terms.size()))) return rc;
+            if ((rc = upload(&s.d_ops, s.plan.ops.data(), s.plan.ops.size()))) return rc;
+            if ((rc = upload(&s.d_monos, s.plan.monos.data(), s.plan.monos.size()))) return rc;
+            if ((rc = upload(&s.d_ranges, rg.data(), rg.size()))) return rc;
+        }
         if ((rc = upload(&s.d_deg1, s.dens.deg1.data(), s.dens.deg1.size()))) return rc;
         if ((rc = upload(&s.d_deg3, s.dens.deg3.data(), s.dens.deg3.size()))) return rc;
         if ((rc = upload(&s.d_W1, s.dens.W1.data(), s.dens.W1.size()))) return rc;
         if ((rc = upload(&s.d_logdeg1, s.dens.logdeg1.data(), s.dens.logdeg1.size()))) return rc;
         s.acc.assign(NSTAT_MAX, 0.0);
         s.built = true;
+        s.has_plan = plans;
     }
     return AMM_OK;
 }
@@ -471,7 +479,7 @@ int amm_build_tables(amm_ctx *c, const amm_density_params *params, int gb, int g
 int amm_plan_stats(const amm_ctx *c, int g, amm_plan_info *out) {
     if (!c || !out || g < 0 || g >= (int)c->slots.size()) return fail(AMM_E_ARG, "amm_plan_stats: bad argument");
     const GraphSlot &s = c->slots[g];
-    if (!s.built) return fail(AMM_E_NOTBUILT, "amm_plan_stats: tables not built");
+    if (!s.has_plan) return fail(AMM_E_NOTBUILT, "amm_plan_stats: integrand tables not built");
     out->n_insertions = s.ne;
     out->n_terms = (int)s.plan.terms.size();
     out->n_terms_expanded = s.plan.n_terms_expanded;
@@ -499,6 +507,7 @@ int amm_sample(amm_ctx *c, int g, uint64_t seed, uint64_t c0, uint64_t n, int le
         case 5: hipLaunchKernelGGL(k_sample<5>, gr, bl, 0, st, D, s.uid, seed, R, c0, n, z, gx, gj, path, comp); break;
         case 8: hipLaunchKernelGGL(k_sample<8>, gr, bl, 0, st, D, s.uid, seed, R, c0, n, z, gx, gj, path, comp); break;
         case 11: hipLaunchKernelGGL(k_sample<11>, gr, bl, 0, st, D, s.uid, seed, R, c0, n, z, gx, gj, path, comp); break;
+        case 14: hipLaunchKernelGGL(k_sample<14>, gr, bl, 0, st, D, s.uid, seed, R, c0, n, z, gx, gj, path, comp); break;
         default: return fail(AMM_E_ARG, "amm_sample: unsupported M");
     }
     HIPCHK(hipGetLastError());
@@ -510,7 +519,7 @@ int amm_eval(amm_ctx *c, int g, const double *z, uint64_t n, double *I, double *
              void *stream) {
     if (!c || g < 0 || g >= (int)c->slots.size()) return fail(AMM_E_ARG, "amm_eval: bad argument");
     GraphSlot &s = c->slots[g];
-    if (!s.built) return fail(AMM_E_NOTBUILT, "amm_eval: tables not built");
+    if (!s.has_plan) return fail(AMM_E_NOTBUILT, "amm_eval: integrand tables not built");
     if (n == 0) return AMM_OK;
     if (!z) return fail(AMM_E_ARG, "amm_eval: z is NULL");
     if (precision < 0 || precision > 2) return fail(AMM_E_ARG, "amm_eval: precision 0, 1 or 2");
@@ -535,7 +544,7 @@ static int check_run(amm_ctx *c, const amm_run_params *r) {
     if (r->graph_begin < 0 || r->graph_end > (int)c->slots.size() || r->graph_begin >= r->graph_end)
         return fail(AMM_E_ARG, "amm_integrate: bad graph range");
     for (int g = r->graph_begin; g < r->graph_end; ++g)
-        if (!c->slots[g].built) return fail(AMM_E_NOTBUILT, "amm_integrate: tables not built");
+        if (!c->slots[g].has_plan) return fail(AMM_E_NOTBUILT, "amm_integrate: integrand tables not built");
     if (c->loops < 1 || c->loops > 4) return fail(AMM_E_ARG, "amm_integrate: unsupported loop order");
     if (c->loops == 1 && r->force_flag)
         return fail(AMM_E_ARG, "amm_integrate: double-double recompute is disabled at 1 loop (force_flag)");
@@ -1016,7 +1025,7 @@ int amm_integrate_adaptive(amm_ctx *c, const amm_run_params *r, uint64_t budget_
         return fail(AMM_E_ARG, "amm_integrate_adaptive: bad graph range");
     const int gb = r->graph_begin, G = r->graph_end - r->graph_begin;
     for (int g = gb; g < r->graph_end; ++g)
-        if (!c->slots[g].built) return fail(AMM_E_NOTBUILT, "amm_integrate_adaptive: tables not built");
+        if (!c->slots[g].has_plan) return fail(AMM_E_NOTBUILT, "amm_integrate_adaptive: integrand tables not built");
     hipStream_t st = (hipStream_t)stream;
     std::vector<double> t(G), Cj(G);
     double tsum = 0.0;
@@ -1095,7 +1104,8 @@ int amm_set_option(amm_ctx *c, int option, int value) {
     } else if (option == AMM_OPT_GENERATOR) {
         if (value != 0 && value != 1) return fail(AMM_E_ARG, "amm_set_option: generator 0 (Philox) or 1 (MRG32k3a)");
         c->generator = value;
-    } else return fail(AMM_E_ARG, "amm_set_option: unknown option");
+    } else if (option == AMM_OPT_PLANS) c->build_plans = value != 0;
+    else return fail(AMM_E_ARG, "amm_set_option: unknown option");
     return AMM_OK;
 }
 

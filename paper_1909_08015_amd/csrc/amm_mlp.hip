@@ -452,7 +452,7 @@ int amm_pilot(amm_ctx *c, uint64_t seed, uint64_t n, int gb, int ge, void *strea
     unsigned long long *Wq = nullptr;
     size_t maxcells = 0;
     for (int g = gb; g < ge; ++g) {
-        if (!c->slots[g].built) return fail(AMM_E_NOTBUILT, "amm_pilot: tables not built");
+        if (!c->slots[g].has_plan) return fail(AMM_E_NOTBUILT, "amm_pilot: integrand tables not built");
         maxcells = std::max(maxcells, ((size_t)1 << c->slots[g].M) * c->slots[g].M);
     }
     HIPCHK(hipMalloc((void **)&wbuf, nbuf * sizeof(double)));

@@ -43,7 +43,7 @@ def oracle_sample(n, gi, counters):
     return d.sample(u)
 
 
-@pytest.mark.parametrize('n', [1, 2, 3])
+@pytest.mark.parametrize('n', [1, 2, 3, 4])
 def test_graph_set_and_classes(amm, n):
     _ctx_for(amm, n, build=False)
     assert amm.n_se == len(G.se_graphs(n))
