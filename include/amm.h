@@ -353,6 +353,15 @@ int amm_pilot_table(const amm_ctx *ctx, int g, double *host, size_t cap);
 int amm_mlp_train(amm_ctx *ctx, int epochs, float lr, uint64_t init_seed, void *stream);
 /* Number of MLP parameters; copy them (FP32) to host buffer (NULL = count only). */
 int amm_mlp_params(const amm_ctx *ctx, float *host, size_t cap, size_t *count);
+/* The same copy under the boundary's name: n floats of room in host_buf. */
+int amm_mlp_get_params(const amm_ctx *ctx, float *host_buf, size_t n);
+/* One Adam step of the training (beta1 = 0.9, beta2 = 0.999, eps = 1e-8,
+ * bias-corrected with step number t >= 1, FP32) on the context's parameters
+ * with a device gradient grad [count floats]; reset_moments = 1 zeroes the
+ * first and second moments first.  Enqueued on `stream`.  For checking the
+ * update against a reference.  Errors: AMM_E_ARG, AMM_E_NOTBUILT (no
+ * parameters yet). */
+int amm_mlp_adam(amm_ctx *ctx, const float *grad, int t, float lr, int reset_moments, void *stream);
 /* Set MLP parameters from a host buffer of `count` floats. */
 int amm_mlp_set_params(amm_ctx *ctx, const float *host, size_t count);
 /* Feature rows of graph g: rows [n_rows x 16] (s, j) features, host output;

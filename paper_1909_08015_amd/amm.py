@@ -84,6 +84,8 @@ SYMBOLS = {
     'amm_mlp_loss_grad': (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
     'amm_set_sector_table': (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    'amm_mlp_get_params': (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    'amm_mlp_adam': (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_float, C.c_int, C.c_void_p]),
     'amm_set_workspace': (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     'amm_workspace_bytes': (C.c_size_t, [C.c_int]),
     'amm_integrate_static': (C.c_int, [C.c_void_p, C.POINTER(RunParams), C.c_void_p]),
@@ -333,6 +335,17 @@ class Context:
         _check(lib().amm_mlp_params(self.h, buf.ctypes.data_as(C.c_void_p), cnt.value, C.byref(cnt)),
                'amm_mlp_params')
         return buf
+
+    def mlp_get_params(self):
+        import numpy as np
+        buf = np.empty(5313, dtype=np.float32)
+        _check(lib().amm_mlp_get_params(self.h, buf.ctypes.data_as(C.c_void_p), buf.size), 'amm_mlp_get_params')
+        return buf
+
+    def mlp_adam(self, grad, t, lr, reset_moments=False, stream=None):
+        """One Adam step of the context's parameters with a device FP32 gradient."""
+        _check(lib().amm_mlp_adam(self.h, _ptr(grad), int(t), float(lr), int(bool(reset_moments)),
+                                  _stream(stream)), 'amm_mlp_adam')
 
     def mlp_set_params(self, p):
         import numpy as np

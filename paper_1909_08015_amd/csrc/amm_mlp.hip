@@ -601,6 +601,26 @@ int amm_mlp_params(const amm_ctx *c, float *host, size_t cap, size_t *count) {
     return AMM_OK;
 }
 
+int amm_mlp_get_params(const amm_ctx *c, float *host_buf, size_t n) {
+    return amm_mlp_params(c, host_buf, n, nullptr);
+}
+
+int amm_mlp_adam(amm_ctx *c, const float *grad, int t, float lr, int reset_moments, void *stream) {
+    if (!c || !grad || t < 1) return fail(AMM_E_ARG, "amm_mlp_adam: bad argument");
+    if (!c->mlp.d_params) return fail(AMM_E_NOTBUILT, "amm_mlp_adam: set parameters first");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(c->device));
+    if (reset_moments) {
+        HIPCHK(hipMemsetAsync(c->mlp.d_m, 0, MLP_NPARAM * sizeof(float), st));
+        HIPCHK(hipMemsetAsync(c->mlp.d_v, 0, MLP_NPARAM * sizeof(float), st));
+    }
+    hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, c->mlp.d_params, grad, c->mlp.d_m,
+                       c->mlp.d_v, t, lr);
+    HIPCHK(hipGetLastError());
+    c->last_stream = st;
+    return AMM_OK;
+}
+
 int amm_mlp_set_params(amm_ctx *c, const float *host, size_t count) {
     if (!c || !host || count != (size_t)MLP_NPARAM) return fail(AMM_E_ARG, "amm_mlp_set_params: bad argument");
     HIPCHK(hipSetDevice(c->device));

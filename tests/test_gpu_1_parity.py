@@ -350,6 +350,35 @@ def test_mlp_gradient_matches_oracle(amm):
     assert float(loss.cpu()) == pytest.approx(lref, rel=1e-4)
     g = grad.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(g - gref) <= 1e-4 * np.linalg.norm(gref)
+    # element by element: FP32 accumulation error relative to the element,
+    # plus a floor at 1e-5 of the largest element for elements near zero
+    err = np.abs(g - gref)
+    assert np.all(err <= 1e-3 * np.abs(gref) + 1e-5 * np.abs(gref).max()), (err / (np.abs(gref) + 1e-30)).max()
+    print('gradient: largest element error / (|g| + 1e-5 max|g|) =',
+          (err / (np.abs(gref) + 1e-5 * np.abs(gref).max())).max())
+
+
+def test_mlp_adam_step_matches_oracle(amm):
+    """Three Adam steps (FP32 kernel) against the oracle's FP64 adam_step on
+    the same parameters and gradients: every parameter within 1e-5 of
+    (|p| + lr), the size of one step."""
+    from oracle import mlp as OM
+    _ctx_for(amm, 2)
+    rng = np.random.default_rng(11)
+    p = OM.init_params(rng.random(OM.NPARAM))
+    amm.mlp_set_params(p)
+    ref = p.astype(np.float64)
+    m = np.zeros(OM.NPARAM)
+    v = np.zeros(OM.NPARAM)
+    lr = 1e-2
+    for t in (1, 2, 3):
+        g = ((rng.random(OM.NPARAM) - 0.5) * 10.0 ** rng.uniform(-6, 0, OM.NPARAM)).astype(np.float32)
+        amm.mlp_adam(torch.tensor(g, device='cuda'), t, lr, reset_moments=(t == 1))
+        ref, m, v = OM.adam_step(ref, g.astype(np.float64), m, v, t, lr)
+    got = amm.mlp_get_params().astype(np.float64)
+    assert np.array_equal(got, amm.mlp_params().astype(np.float64))
+    assert np.all(np.abs(got - ref) <= 1e-5 * (np.abs(ref) + lr)), np.abs(got - ref).max()
+    assert np.abs(got - p).max() > lr      # the steps moved the parameters
 
 
 def test_generated_code_matches_interpreter(amm):

@@ -98,29 +98,31 @@ def test_learned_sampler_2_loops_reproduces_closed_form(amm):
 
 
 def test_learned_sampler_unbiased_and_gain(amm):
-    """3-loop set: pilot (seed 1) -> GPU training -> learned mixture on seed 0.
-    Per graph the learned estimate agrees with the plain one within 5 combined
-    sigma; the summed variance times time is reported and must not be worse
-    than the plain density's by more than the 50/50 mixture's worst case."""
+    """3-loop set: pilot (seed 1) -> GPU training -> learned mixture.  Per graph
+    the learned estimate agrees with the plain one within 5 combined sigma on
+    every seed.  Gain: the summed variance (graph sigmas from the per-point
+    totals over insertions) times the run time, learned over plain, on three
+    measurement seeds at 2^22 samples per graph; its median must be below 0.5
+    and every seed below 0.8 (measured: about 0.25)."""
     amm.enumerate(3)
     amm.build_tables()
-    G = amm.n_se
     amm.integrate(seed=1, n_per_graph=50_000, force_flag=1)
-    N = 1 << 21
+    N = 1 << 22
     tau = amm.accept_thresholds(N)
     amm.pilot(1, 1_000_000)
     amm.mlp_train(300, lr=1e-2, init_seed=0)
-    plain, tp = _run(amm, 0, N, tau)
-    learned, tl = _run(amm, 1, N, tau)
-    _run(amm, 0, N, tau)                      # timing after warm caches
-    plain, tp = _run(amm, 0, N, tau)
-    learned, tl = _run(amm, 1, N, tau)
-    for p, l in zip(plain, learned):
-        s = math.sqrt(p['sigma'] ** 2 + l['sigma'] ** 2)
-        assert abs(p['mean'] - l['mean']) <= 5 * s, (p, l)
-    vp = sum(p['sigma'] ** 2 for p in plain)
-    vl = sum(l['sigma'] ** 2 for l in learned)
-    ratio = (vl * tl) / (vp * tp)
-    print(f'\n3-loop sigma^2: plain {vp:.4e} learned {vl:.4e}; time plain {tp:.3f}s learned {tl:.3f}s; '
-          f'sigma^2*time learned/plain = {ratio:.3f}')
-    assert ratio < 2.5
+    _run(amm, 0, N, tau)                      # warm caches before timing
+    _run(amm, 1, N, tau)
+    ratios = []
+    for seed in (0, 2, 3):
+        plain, tp = _run(amm, 0, N, tau, seed=seed)
+        learned, tl = _run(amm, 1, N, tau, seed=seed)
+        for p, l in zip(plain, learned):
+            s = math.sqrt(p['sigma'] ** 2 + l['sigma'] ** 2)
+            assert abs(p['mean'] - l['mean']) <= 5 * s, (seed, p, l)
+        vp = sum(p['sigma'] ** 2 for p in plain)
+        vl = sum(l['sigma'] ** 2 for l in learned)
+        ratios.append((vl * tl) / (vp * tp))
+        print(f'\nseed {seed}: 3-loop sigma^2 plain {vp:.4e} learned {vl:.4e}; time plain {tp:.3f}s '
+              f'learned {tl:.3f}s; sigma^2*time learned/plain = {ratios[-1]:.3f}')
+    assert sorted(ratios)[1] < 0.5 and max(ratios) < 0.8, ratios
