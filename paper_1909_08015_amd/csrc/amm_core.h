@@ -552,28 +552,119 @@ AMM_HDI MonoRegs load_mono(const Mono *p) {
     return r;
 }
 
+// Index shared by the lanes of a wave.  The FP64 interpreter paths run every
+// lane of a wave on the same graph, term and level (one graph per launch or
+// per chunk), so the monomial ranges are wave-uniform and the table reads can
+// be scalar.
+AMM_HDI int wave_uniform(int x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_readfirstlane(x);
+#else
+    return x;
+#endif
+}
+
+// Sum of a range in FP64 (Tv = double) or FP64 with the first-order bound
+// (Tv = ea), four monomials at a time on independent accumulators: their
+// variable reads and products are in flight together.  Past its degree a
+// monomial reads variable 0 and multiplies by exactly 1 (branch-free).  The
+// four partial sums are added at the end; for the bound each addition adds
+// |its result|.
+// A monomial at a wave-uniform address, read with scalar loads (the table
+// words land in scalar registers, so decoding the variable indices costs no
+// vector instructions).
+AMM_HDI MonoRegs load_mono_uniform(const Mono *p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint64_t a = (uint64_t)(const void *)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a), hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    typedef const uint64_t __attribute__((address_space(4))) *cptr;
+    const cptr q = (cptr)(((uint64_t)hi << 32) | lo);
+    MonoRegs r;
+    r.coef = __builtin_bit_cast(double, q[0]);
+    r.w1 = q[1];
+    r.w2 = q[2];
+    return r;
+#else
+    return load_mono(p);
+#endif
+}
+
+// Sum of a range in FP64 (Bound = false) or FP64 with the first-order bound,
+// four monomials at a time on independent accumulators so that their variable
+// reads and products are in flight together; the range, the table words and
+// the degrees are wave-uniform, so the degree tests are scalar branches.  The
+// bound term of a monomial, |p| (nv (rmax + 1) + 1), is kept as the two sums
+// of |p| nv and |p|; each accumulation adds |partial sum|, and so does each
+// addition of the four partial sums at the end.
+template <bool Bound, typename Vars>
+AMM_HDI void poly_sum4(const PlanDev &P, int2 r, const Vars &vars, double r1, double &sum, double &err) {
+    const int beg = wave_uniform(r.x), end = wave_uniform(r.y);
+    double av[4] = {0.0, 0.0, 0.0, 0.0}, an[4] = {0.0, 0.0, 0.0, 0.0}, aa[4] = {0.0, 0.0, 0.0, 0.0};
+    int m = beg;
+    for (; m + 4 <= end; m += 4) {
+        MonoRegs mo[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mo[q] = load_mono_uniform(P.monos + m + q);
+        int k[4], kmin = MAXMONO_VARS + 1, kmax = 0;
+        double p[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            k[q] = mo[q].nv();
+            kmax = k[q] > kmax ? k[q] : kmax;
+            kmin = k[q] < kmin ? k[q] : kmin;
+            p[q] = mo[q].coef;
+        }
+        // ranges are sorted by degree, so the four degrees nearly always agree
+        int i = 0;
+        for (; i < kmin; ++i) {
+            double x[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = vars.val(mo[q].var(i));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) p[q] = p[q] * x[q];
+        }
+        for (; i < kmax; ++i) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (i < k[q]) p[q] = p[q] * vars.val(mo[q].var(i));
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            av[q] = av[q] + p[q];
+            if (Bound) {
+                an[q] = fma(fabs(p[q]), (double)k[q], an[q]);
+                aa[q] = (aa[q] + fabs(p[q])) + fabs(av[q]);
+            }
+        }
+    }
+    for (; m < end; ++m) {
+        const MonoRegs mo = load_mono_uniform(P.monos + m);
+        const int nv = mo.nv();
+        double p = mo.coef;
+        for (int i = 0; i < nv; ++i) p = p * vars.val(mo.var(i));
+        av[0] = av[0] + p;
+        if (Bound) {
+            an[0] = fma(fabs(p), (double)nv, an[0]);
+            aa[0] = (aa[0] + fabs(p)) + fabs(av[0]);
+        }
+    }
+    const double s01 = av[0] + av[1], s23 = av[2] + av[3];
+    sum = s01 + s23;
+    if (Bound)
+        err = fma((an[0] + an[1]) + (an[2] + an[3]), r1, (aa[0] + aa[1]) + (aa[2] + aa[3])) +
+              ((fabs(s01) + fabs(s23)) + fabs(sum));
+}
+
 template <typename T, typename Vars>
 AMM_HDI T poly_range(const PlanDev &P, int2 r, const Vars &vars, double rmax) {
     if constexpr (std::is_same<T, ea>::value) {
         double av = 0.0, ae = 0.0;
-        const double r1 = rmax + 1.0;
-        MonoRegs nxt = load_mono(P.monos + (r.x < r.y ? r.x : 0));
-        for (int m = r.x; m < r.y; ++m) {
-            const MonoRegs mo = nxt;
-            nxt = load_mono(P.monos + (m + 1 < r.y ? m + 1 : m));      // next monomial in flight
-            const int nv = mo.nv();
-            double p = mo.coef;
-            int i = 0;
-            for (; i + 2 <= nv; i += 2) {           // two variable reads in flight
-                const double a = vars.val(mo.var(i)), b = vars.val(mo.var(i + 1));
-                p = p * a;
-                p = p * b;
-            }
-            if (i < nv) p = p * vars.val(mo.var(i));
-            av = av + p;
-            ae = fma(fabs(p), fma((double)nv, r1, 1.0), ae) + fabs(av);
-        }
+        poly_sum4<true>(P, r, vars, rmax + 1.0, av, ae);
         return ea(av, ae);
+    } else if constexpr (std::is_same<T, double>::value) {
+        double av = 0.0, ae = 0.0;
+        poly_sum4<false>(P, r, vars, 0.0, av, ae);
+        return av;
     } else if constexpr (std::is_same<T, dd>::value) {
         // two monomials per step on separate accumulators (independent
         // dependency chains), the next two already loading
@@ -659,6 +750,7 @@ struct VarsLdsD {
     AMM_HDI void begin() {}
     AMM_HDI void set(int i, double x) { base[i * stride] = x; }
     AMM_HDI double get(int i) const { return base[i * stride]; }
+    AMM_HDI double val(int i) const { return base[i * stride]; }
 };
 struct VarsLdsEa {
     double *base;      // values, one LDS column per thread

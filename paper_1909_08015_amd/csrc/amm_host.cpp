@@ -750,7 +750,7 @@ void build_plan(const SEGraph &g, PlanHost &P) {
                         base = (int)P.poly_ranges_store.size();
                         for (int o = 0; o < d.nout; ++o) {
                             for (int c = 0; c <= n; ++c) {
-                                int beg = (int)P.monos.size();
+                                const int beg = (int)P.monos.size();
                                 for (auto &kv : lp.out[o]) {
                                     if ((int)kv.first.pairs.size() != c || kv.second == 0) continue;
                                     Mono m;
@@ -766,6 +766,9 @@ void build_plan(const SEGraph &g, PlanHost &P) {
                                     m.nv = (uint8_t)nv;
                                     P.monos.push_back(m);
                                 }
+                                // degree-sorted ranges: the kernels read monomials of equal degree together
+                                std::stable_sort(P.monos.begin() + beg, P.monos.end(),
+                                                 [](const Mono &x, const Mono &y) { return x.nv > y.nv; });
                                 P.poly_ranges_store.push_back({beg, (int)P.monos.size()});
                             }
                         }
