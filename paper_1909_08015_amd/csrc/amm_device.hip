@@ -713,10 +713,10 @@ static void enqueue_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, con
             const int grid = std::min(nch, grid_target);
             hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.work, 0);
             switch (c->loops) {
-                case 1: hipLaunchKernelGGL(k_integrate_fused<1>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
-                case 2: hipLaunchKernelGGL(k_integrate_fused<2>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
-                case 3: hipLaunchKernelGGL(k_integrate_fused<3>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
-                case 4: hipLaunchKernelGGL(k_integrate_fused<4>, dim3(grid), dim3(BLOCK), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
+                case 1: hipLaunchKernelGGL(k_integrate_fused<1>, dim3(grid), dim3(InterpEval::kBlock), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
+                case 2: hipLaunchKernelGGL(k_integrate_fused<2>, dim3(grid), dim3(InterpEval::kBlock), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
+                case 3: hipLaunchKernelGGL(k_integrate_fused<3>, dim3(grid), dim3(InterpEval::kBlock), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
+                case 4: hipLaunchKernelGGL(k_integrate_fused<4>, dim3(grid), dim3(InterpEval::kBlock), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
             }
         } else {
             // one launch per segment; they write disjoint chunks, so they run

@@ -17,6 +17,9 @@ namespace amm {
 // Evaluator using the plan tables (variables in LDS columns).
 struct InterpEval {
     static constexpr bool kLds = true;
+    // Monte Carlo block size: 64-thread blocks keep the LDS variable columns
+    // of a block at 64 x NV doubles, so more blocks fit on a compute unit
+    static constexpr int kBlock = 64;
     PlanDev P;
     template <typename T, int N, typename Vars>
     __device__ __forceinline__ void eval(const double *z, T *I, T *absI, Vars &vars) const {
@@ -28,6 +31,7 @@ struct InterpEval {
 template <class G>
 struct GenEval {
     static constexpr bool kLds = false;
+    static constexpr int kBlock = BLOCK;
     template <typename T, int N, typename Vars>
     __device__ __forceinline__ void eval(const double *z, T *I, T *absI, Vars &) const {
         G::template eval<T>(z, I, absI);
@@ -138,6 +142,7 @@ __device__ __forceinline__ void add_stats(double (&st)[nstat_of(2 * N - 1, 2 * N
 template <int N, class Ev>
 __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, const RunArgs &A, uint64_t idx,
                                             double *y, int &ood, int &flag, int &ddbad, double *vlds) {
+    constexpr int NB = Ev::kBlock;
     constexpr int M = 3 * N - 1, NE = 2 * N - 1;
     double u[2 * M], z[M];
     int path[M];
@@ -155,7 +160,7 @@ __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, c
     if (plain) {
         if constexpr (Ev::kLds) {
             double I[NE], aI[NE];
-            VarsLdsD vars{vlds + threadIdx.x, BLOCK};
+            VarsLdsD vars{vlds + threadIdx.x, NB};
             EV.template eval<double, N>(z, I, aI, vars);
             for (int e = 0; e < NE; ++e) {
                 y[e] = ldexp(I[e] / o.gx, -o.gj);
@@ -166,7 +171,7 @@ __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, c
     } else {
         ea I[NE], aI[NE];
         if constexpr (Ev::kLds) {
-            VarsLdsEa vars{vlds + threadIdx.x, BLOCK, 0.0};
+            VarsLdsEa vars{vlds + threadIdx.x, NB, 0.0};
             EV.template eval<ea, N>(z, I, aI, vars);
         } else {
             VarsPriv<ea, 1> vars;
@@ -220,7 +225,7 @@ __device__ __forceinline__ void block_stats(const double (&st)[NST], int nst, do
 
 // One chunk (CHUNK consecutive samples, local chunk ch of the run A): FP64
 // pass, acceptance, flag compaction in sample order, per-chunk sums.  Called
-// by every thread of a BLOCK-thread block.
+// by every thread of an Ev::kBlock-thread block.
 template <int N, class Ev>
 __device__ __forceinline__ void process_chunk(const Ev &EV, const DensityDev &D, const RunArgs &A, int ch,
                                               double *part_ch, uint32_t *flags_ch, int32_t *nflag_ch,
@@ -228,7 +233,7 @@ __device__ __forceinline__ void process_chunk(const Ev &EV, const DensityDev &D,
                                               double *vlds) {
     constexpr int NE = 2 * N - 1;
     constexpr int NST = nstat_of(NE, NE);
-    constexpr int NW = BLOCK / 64;
+    constexpr int NB = Ev::kBlock, NW = NB / 64, RND = CHUNK / NB;
     const int nst = nstat_of(NE, A.ncls);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double st[NST];
@@ -237,8 +242,8 @@ __device__ __forceinline__ void process_chunk(const Ev &EV, const DensityDev &D,
     const uint64_t local0 = (uint64_t)(A.chunk0 + ch) * CHUNK;
     const uint64_t base = base_offset(A) + A.begin + local0;
     int fcount = 0;
-    for (int r = 0; r < RPC; ++r) {
-        const uint64_t off = (uint64_t)r * BLOCK + threadIdx.x;
+    for (int r = 0; r < RND; ++r) {
+        const uint64_t off = (uint64_t)r * NB + threadIdx.x;
         int flag = 0, ood = 0, ddbad = 0;
         double y[NE];
         const bool live = local0 + off < n_run;
@@ -260,19 +265,20 @@ __device__ __forceinline__ void process_chunk(const Ev &EV, const DensityDev &D,
         for (int w = 0; w < NW; ++w) fcount += shw[w];
         __syncthreads();
     }
-    block_stats<NST, BLOCK>(st, nst, shs, part_ch, false);
+    block_stats<NST, NB>(st, nst, shs, part_ch, false);
     if (threadIdx.x == 0) *nflag_ch = fcount;
 }
 
 // FP64 pass of one segment: blocks stride over its chunks.
 template <int N, class Ev>
-__global__ void __launch_bounds__(BLOCK) k_integrate(Ev EV, DensityDev D, RunArgs A, double *part, uint32_t *flags,
-                                                     int32_t *nflag) {
+__global__ void __launch_bounds__(Ev::kBlock) k_integrate(Ev EV, DensityDev D, RunArgs A, double *part,
+                                                          uint32_t *flags, int32_t *nflag) {
     constexpr int NE = 2 * N - 1;
     constexpr int NST = nstat_of(NE, NE);
-    __shared__ double shs[BLOCK / 64][NST];
-    __shared__ int shw[BLOCK / 64];
-    __shared__ double vlds[(Ev::kLds ? Dims<N>::NV : 1) * BLOCK];
+    constexpr int NB = Ev::kBlock;
+    __shared__ double shs[NB / 64][NST];
+    __shared__ int shw[NB / 64];
+    __shared__ double vlds[(Ev::kLds ? Dims<N>::NV : 1) * NB];
     for (int ch = blockIdx.x; ch < A.nchunks; ch += gridDim.x)
         process_chunk<N>(EV, D, A, ch, part + (size_t)ch * NSTAT_MAX, flags + (size_t)ch * CHUNK, nflag + ch, shs,
                          shw, vlds);
@@ -283,13 +289,15 @@ __global__ void __launch_bounds__(BLOCK) k_integrate(Ev EV, DensityDev D, RunArg
 // are ordered heaviest graph first when grouping by cost).  Every block exits
 // once the counter passes the group's chunk count.
 template <int N>
-__global__ void __launch_bounds__(BLOCK) k_integrate_fused(const SegDev *segs, int nseg, int nch, int *work,
-                                                           double *part, uint32_t *flags, int32_t *nflag) {
+__global__ void __launch_bounds__(InterpEval::kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_integrate_fused(const SegDev *segs, int nseg, int nch,
+                                                                       int *work, double *part, uint32_t *flags,
+                                                                       int32_t *nflag) {
     constexpr int NE = 2 * N - 1;
     constexpr int NST = nstat_of(NE, NE);
-    __shared__ double shs[BLOCK / 64][NST];
-    __shared__ int shw[BLOCK / 64];
-    __shared__ double vlds[Dims<N>::NV * BLOCK];
+    constexpr int NB = InterpEval::kBlock;
+    __shared__ double shs[NB / 64][NST];
+    __shared__ int shw[NB / 64];
+    __shared__ double vlds[Dims<N>::NV * NB];
     __shared__ int item;
     for (;;) {
         if (threadIdx.x == 0) item = atomicAdd(work, 1);
@@ -487,7 +495,7 @@ static __global__ void __launch_bounds__(256) k_reduce_seg(const SegDev *segs, c
 template <int N, class Ev>
 void launch_fp64_ev(const Ev &EV, const DensityDev &D, const RunArgs &A, int grid, double *part, uint32_t *flag,
                     int32_t *nflag, hipStream_t s) {
-    hipLaunchKernelGGL((k_integrate<N, Ev>), dim3(grid), dim3(BLOCK), 0, s, EV, D, A, part, flag, nflag);
+    hipLaunchKernelGGL((k_integrate<N, Ev>), dim3(grid), dim3(Ev::kBlock), 0, s, EV, D, A, part, flag, nflag);
 }
 
 // Double-double recompute of the flagged samples of a group (scan, per-point
