@@ -6,10 +6,11 @@
 // eval_graph) does -- same levels, same operation order inside each level,
 // same numerator polynomials -- but with every index, span and loop bound
 // resolved at generation time, so all intermediate values live in
-// registers.  Identical level subtrees (same level, same children) are
-// evaluated once per point and shared by the terms that contain them.
+// registers.  Each forest term is its own non-inlined device function; a
+// term's levels are evaluated inside it (identical subtrees of different
+// terms are evaluated again, as in the interpreter).
 //
-// Usage: amm_codegen <loops> <out.hip>
+// Usage: amm_codegen graph <loops> <g> <dir> | dispatch <out.hip> <loops>...
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
