@@ -122,8 +122,9 @@ int amm_graph_desc(const amm_ctx *ctx, int g, int *chords, int *classes);
 /* Build the per-graph density tables (Sec. III.A) and subtraction tables
  * (Sec. II forest formula) for graphs [graph_begin, graph_end) of the
  * enumerated loop order and upload them once.  params NULL = Calc 2.
- * Integrand tables exist for 1-4 loops; at 5 loops only the density tables
- * are built (AMM_OPT_PLANS = 0), else AMM_E_TOOBIG. */
+ * At 5 loops the integrand tables hold about 3 million monomials (70 MB) per
+ * graph and take minutes per graph to build on one host core (graphs are
+ * built on a thread pool); AMM_OPT_PLANS = 0 builds the density tables alone. */
 int amm_build_tables(amm_ctx *ctx, const amm_density_params *params,
                      int graph_begin, int graph_end);
 
@@ -216,8 +217,8 @@ size_t amm_workspace_bytes(int chunks_per_group);
  *   (amm_pilot) always uses Philox4x32-10.
  * AMM_OPT_PLANS (default 1): amm_build_tables builds the integrand tables as
  *   well as the density tables; 0 builds the density tables only (sampling
- *   with amm_sample, e.g. at 5 loops, where integrand tables are not built);
- *   amm_eval, amm_integrate* and amm_pilot then return AMM_E_NOTBUILT. */
+ *   with amm_sample, e.g. for all 706 graphs at 5 loops); amm_eval,
+ *   amm_integrate* and amm_pilot then return AMM_E_NOTBUILT. */
 #define AMM_OPT_GENERATED 1
 #define AMM_OPT_FUSED 2
 #define AMM_OPT_ORDER_BY_COST 3

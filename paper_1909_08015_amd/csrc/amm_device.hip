@@ -212,7 +212,7 @@ void launch_eval(const GraphSlot &gs, int g, const double *z, uint64_t n, double
         return;
     }
     if (prec == 2) {
-        launch_eval_ev<N, InterpEval, iv>(EV, z, n, I, a, b, s);
+        if constexpr (N <= 4) launch_eval_ev<N, InterpEval, iv>(EV, z, n, I, a, b, s);
         return;
     }
     if (use_gen && gen_launch(N, g)) {
@@ -400,9 +400,6 @@ int amm_build_tables(amm_ctx *c, const amm_density_params *params, int gb, int g
     if (!c || c->loops == 0) return fail(AMM_E_ARG, "amm_build_tables: call amm_enumerate first");
     if (gb < 0 || ge > (int)c->graphs.size() || gb >= ge) return fail(AMM_E_ARG, "amm_build_tables: bad graph range");
     const bool plans = c->build_plans != 0;
-    if (c->loops > 4 && plans)
-        return fail(AMM_E_TOOBIG, "amm_build_tables: integrand tables are built for 1..4 loops "
-                                  "(density tables only: AMM_OPT_PLANS = 0)");
     amm_density_params p;
     if (params) p = *params;
     else p = amm_density_params{0.256, 0.839, 0.786, 0.2, 0.0, 0.2, {((1.0 - 0.03) - 0.01) - 0.06, 0.03, 0.01, 0.06}, 0.75, 1.0};
@@ -411,19 +408,21 @@ int amm_build_tables(amm_ctx *c, const amm_density_params *params, int gb, int g
     {
         std::atomic<int> next(gb);
         std::vector<std::string> errs(ge - gb);
+        const unsigned hw = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 16u));
+        unsigned nt = std::min<unsigned>(hw, (unsigned)(ge - gb));
+        // few graphs: each one's distinct level polynomials on several threads
+        const int inner = (int)std::max(1u, hw / nt);
         auto work = [&]() {
             for (int g = next++; g < ge; g = next++) {
                 try {
                     build_density(c->graphs[g], p, c->slots[g].dens);
-                    if (plans) build_plan(c->graphs[g], c->slots[g].plan);
+                    if (plans) build_plan(c->graphs[g], c->slots[g].plan, inner);
                     else c->slots[g].plan = PlanHost();
                 } catch (const std::exception &ex) {
                     errs[g - gb] = ex.what();
                 }
             }
         };
-        unsigned nt = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 16u));
-        nt = std::min<unsigned>(nt, (unsigned)(ge - gb));
         std::vector<std::thread> pool;
         for (unsigned t = 1; t < nt; ++t) pool.emplace_back(work);
         work();
@@ -531,6 +530,10 @@ int amm_eval(amm_ctx *c, int g, const double *z, uint64_t n, double *I, double *
         case 2: launch_eval<2>(s, g, z, n, I, absI, bound, precision, st, c->use_gen); break;
         case 3: launch_eval<3>(s, g, z, n, I, absI, bound, precision, st, c->use_gen); break;
         case 4: launch_eval<4>(s, g, z, n, I, absI, bound, precision, st, c->use_gen); break;
+        case 5:
+            if (precision == 2) return fail(AMM_E_ARG, "amm_eval: interval evaluation is built for 1-4 loops");
+            launch_eval<5>(s, g, z, n, I, absI, bound, precision, st, c->use_gen);
+            break;
         default: return fail(AMM_E_ARG, "amm_eval: unsupported loop order");
     }
     HIPCHK(hipGetLastError());
@@ -545,7 +548,7 @@ static int check_run(amm_ctx *c, const amm_run_params *r) {
         return fail(AMM_E_ARG, "amm_integrate: bad graph range");
     for (int g = r->graph_begin; g < r->graph_end; ++g)
         if (!c->slots[g].has_plan) return fail(AMM_E_NOTBUILT, "amm_integrate: integrand tables not built");
-    if (c->loops < 1 || c->loops > 4) return fail(AMM_E_ARG, "amm_integrate: unsupported loop order");
+    if (c->loops < 1 || c->loops > 5) return fail(AMM_E_ARG, "amm_integrate: unsupported loop order");
     if (c->loops == 1 && r->force_flag)
         return fail(AMM_E_ARG, "amm_integrate: double-double recompute is disabled at 1 loop (force_flag)");
     if (r->blocks_per_cu < 0 || r->blocks_per_cu > 64) return fail(AMM_E_ARG, "amm_integrate: blocks_per_cu 0..64");
@@ -717,6 +720,7 @@ static void enqueue_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, con
                 case 2: hipLaunchKernelGGL(k_integrate_fused<2>, dim3(grid), dim3(InterpEval::kBlock), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
                 case 3: hipLaunchKernelGGL(k_integrate_fused<3>, dim3(grid), dim3(InterpEval::kBlock), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
                 case 4: hipLaunchKernelGGL(k_integrate_fused<4>, dim3(grid), dim3(InterpEval::kBlock), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
+                case 5: hipLaunchKernelGGL(k_integrate_fused<5>, dim3(grid), dim3(InterpEval::kBlock), 0, st, d_segs + k0, k1 - k0, nch, ws.work, ws.part, ws.flag, ws.nflag); break;
             }
         } else {
             // one launch per segment; they write disjoint chunks, so they run
@@ -739,6 +743,7 @@ static void enqueue_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, con
                     case 2: launch_seg_fp64<2>(c->slots[segs[k].g], segs[k], grid, ws, ls, c->use_gen); break;
                     case 3: launch_seg_fp64<3>(c->slots[segs[k].g], segs[k], grid, ws, ls, c->use_gen); break;
                     case 4: launch_seg_fp64<4>(c->slots[segs[k].g], segs[k], grid, ws, ls, c->use_gen); break;
+                    case 5: launch_seg_fp64<5>(c->slots[segs[k].g], segs[k], grid, ws, ls, c->use_gen); break;
                 }
             }
             if (ns > 1)
@@ -754,6 +759,7 @@ static void enqueue_run(amm_ctx *c, const amm_run_params *r, hipStream_t st, con
             case 2: launch_group_tail<2>(c, ws, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
             case 3: launch_group_tail<3>(c, ws, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
             case 4: launch_group_tail<4>(c, ws, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
+            case 5: launch_group_tail<5>(c, ws, d_segs + k0, k1 - k0, nch, grid_red, st, evp); break;
         }
         if (evp) {
             hipEventRecord(ev.d, st);

@@ -25,6 +25,8 @@
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
+#include <thread>
+#include <atomic>
 
 namespace amm {
 
@@ -673,7 +675,57 @@ void build_density(const SEGraph &g, const amm_density_params &p, DensityTables 
 // ---------------------------------------------------------------------------
 // Plan assembly
 // ---------------------------------------------------------------------------
-void build_plan(const SEGraph &g, PlanHost &P) {
+// The distinct level polynomials of a graph (chain and operator of every
+// level variant of every term), built on `nthreads` threads: each distinct
+// chain once, in parallel (each thread has its own trace memo).
+static std::map<std::string, LevelPoly> build_graph_polys(const SEGraph &g, int nthreads) {
+    const int n = g.n;
+    std::vector<std::string> keys;
+    std::vector<std::pair<std::vector<Item>, int>> jobs;
+    std::map<std::string, int> seen;
+    for (int e = 0; e < 2 * n - 1; ++e) {
+        VG vg = make_vg(g, e);
+        for (auto &t : build_terms(vg, nullptr)) {
+            std::vector<int> parent;
+            auto lv = build_levels(vg, t, parent);
+            for (auto &L : lv) {
+                int nse = 0;
+                for (int kid : L.kids) if (t.forest[kid].se) ++nse;
+                const int K = (int)L.nodes.size() - 1;
+                for (int var = 0; var < (1 << nse); ++var) {
+                    auto items = level_chain(vg, L, t.forest, lv, (unsigned)var);
+                    std::string key = poly_key(items, L.op) + "K" + std::to_string(K);
+                    if (seen.emplace(key, (int)keys.size()).second) {
+                        keys.push_back(key);
+                        jobs.push_back({items, L.op});
+                    }
+                }
+            }
+        }
+    }
+    std::vector<LevelPoly> polys(jobs.size());
+    std::vector<std::string> errs(nthreads > 0 ? nthreads : 1);
+    std::atomic<size_t> next(0);
+    auto work = [&](int w) {
+        try {
+            for (size_t i = next++; i < jobs.size(); i = next++) polys[i] = build_level_poly(jobs[i].first, jobs[i].second);
+        } catch (const std::exception &ex) {
+            errs[w] = ex.what();
+        }
+    };
+    const int nt = std::max(1, std::min<int>(nthreads, (int)jobs.size()));
+    std::vector<std::thread> pool;
+    for (int w = 1; w < nt; ++w) pool.emplace_back(work, w);
+    work(0);
+    for (auto &th : pool) th.join();
+    for (auto &e : errs)
+        if (!e.empty()) throw std::runtime_error(e);
+    std::map<std::string, LevelPoly> out;
+    for (size_t i = 0; i < keys.size(); ++i) out.emplace(keys[i], std::move(polys[i]));
+    return out;
+}
+
+void build_plan(const SEGraph &g, PlanHost &P, int nthreads) {
     int n = g.n;
     P.n = n;
     P.M = 3 * n - 1;
@@ -682,7 +734,7 @@ void build_plan(const SEGraph &g, PlanHost &P) {
     P.n_terms_expanded = 0;
     P.n_monos_per_sample = 0;
     P.flops_per_sample = 0;
-    std::map<std::string, int> poly_cache;   // key -> first range index block
+    const std::map<std::string, LevelPoly> built = build_graph_polys(g, nthreads);
     std::map<std::string, std::pair<int, int>> poly_cache_n;   // key -> (nvar-independent) (range base, count)
     for (int e = 0; e < 2 * n - 1; ++e) {
         VG vg = make_vg(g, e);
@@ -746,7 +798,7 @@ void build_plan(const SEGraph &g, PlanHost &P) {
                     auto it = poly_cache_n.find(key);
                     int base;
                     if (it == poly_cache_n.end()) {
-                        LevelPoly lp = build_level_poly(items, L.op);
+                        const LevelPoly &lp = built.at(key);
                         base = (int)P.poly_ranges_store.size();
                         for (int o = 0; o < d.nout; ++o) {
                             for (int c = 0; c <= n; ++c) {

@@ -56,7 +56,9 @@ double host_log(double x);
 std::vector<SEGraph> enumerate_se(int n);
 std::array<int, 3> vertex_class(const SEGraph &g, int e);
 void build_density(const SEGraph &g, const amm_density_params &p, DensityTables &d);
-void build_plan(const SEGraph &g, PlanHost &P);
+// nthreads: host threads that build the graph's distinct level polynomials
+// (the result does not depend on it).
+void build_plan(const SEGraph &g, PlanHost &P, int nthreads = 1);
 double omega_set(const SEGraph &g, uint32_t mask);
 void set_stats(const SEGraph &g, uint32_t mask, int *loops, int *comps, int *ng, int *ne);
 

@@ -5,13 +5,19 @@ for every 3-loop SE graph and Philox seed 0, sample counters [0, N_PER_GRAPH):
 the sums of eq. (integral_approx) and eq. (sigma_down) per insertion, per class
 (insertions of the class summed at each point) and for the per-point total,
 plus the out-of-double count.  Every integrand is evaluated in x87 extended
-precision (64-bit significand) and rounded to double before y = I / g, so the
-sums are those of (nearly) exact integrands, whichever points an FP64 pass
-would have flagged.
+precision (64-bit significand) and rounded to double before y = I / g.  The
+forest sum cancels pointwise (Sec. II): the x87 value of y carries an error of
+about 2^-64 times sum|terms|/g, which reaches O(1) and beyond near the
+boundaries (sum|terms|/g up to 1e17 against |y| of 1e-3).  Points whose
+sum|terms|/g exceeds EXACT_ABOVE are evaluated exactly (rational arithmetic)
+instead, so every y is within about 1e-6 of the exact value and the sums are
+those of (nearly) exact integrands, whichever points an FP64 pass would have
+flagged.
 
-Run: python tests/golden/make_golden_estimates.py   (about 5 minutes on 8 cores)
+Run: python tests/golden/make_golden_estimates.py   (about 30 minutes on 8 cores)
 """
 import json
+from fractions import Fraction
 import os
 import sys
 from multiprocessing import Pool
@@ -29,6 +35,7 @@ from oracle.estimate import DBL_MIN, classes_of   # noqa: E402
 N_LOOPS = 3
 N_PER_GRAPH = 1 << 20
 CHUNK = 1 << 15
+EXACT_ABOVE = 1e10
 
 
 def job(args):
@@ -39,14 +46,21 @@ def job(args):
     zl = [np.asarray(z[:, i], dtype=np.longdouble) for i in range(z.shape[1])]
     ne = 2 * N_LOOPS - 1
     vals = np.zeros((CHUNK, ne))
+    absv = np.zeros((CHUNK, ne))
     with np.errstate(all='ignore'):
         for e in range(ne):
-            v, _ = I.vertex_integrand(G.make_vertex_graph(ch, e), zl, exact='ld')
+            v, a = I.vertex_integrand(G.make_vertex_graph(ch, e), zl, exact='ld')
             vals[:, e] = np.broadcast_to(np.asarray(v, dtype=np.longdouble), (CHUNK,)).astype(np.float64)
+            absv[:, e] = np.broadcast_to(np.asarray(a, dtype=np.longdouble), (CHUNK,)).astype(np.float64)
         y = np.ldexp(vals / out['gx'][:, None], -out['gj'][:, None])
+        scale = np.ldexp(absv / out['gx'][:, None], -out['gj'][:, None]).max(1)
     bad = (z.min(1) < DBL_MIN) | ~np.all(np.isfinite(y), 1)
+    redo = np.where(~bad & ~(scale <= EXACT_ABOVE))[0]
+    for i in redo:
+        ex = I.se_integrands(N_LOOPS, gi, [Fraction(x) for x in z[i]], exact=True)
+        y[i] = [np.ldexp(float(v) / out['gx'][i], -int(out['gj'][i])) for v, _ in ex]
     y[bad] = 0.0
-    return gi, c0, y, int(bad.sum())
+    return gi, c0, y, int(bad.sum()), len(redo)
 
 
 def main():
@@ -55,8 +69,8 @@ def main():
     jobs = [(gi, c0) for gi in range(ngr) for c0 in range(0, N_PER_GRAPH, CHUNK)]
     res = {}
     with Pool(int(os.environ.get('AMM_GOLDEN_JOBS', '8'))) as pool:
-        for gi, c0, y, nbad in pool.imap_unordered(job, jobs, chunksize=1):
-            res[(gi, c0)] = (y, nbad)
+        for gi, c0, y, nbad, nexact in pool.imap_unordered(job, jobs, chunksize=1):
+            res[(gi, c0)] = (y, nbad, nexact)
     out = {'loops': N_LOOPS, 'seed': 0, 'n_per_graph': N_PER_GRAPH, 'graphs': []}
     for gi in range(ngr):
         cls = classes_of(N_LOOPS, gi)
@@ -65,17 +79,18 @@ def main():
         s = np.zeros(2 * N_LOOPS - 1); s2 = np.zeros_like(s)
         cs = {c: 0.0 for c in ucls}; cs2 = {c: 0.0 for c in ucls}
         ts = ts2 = 0.0
-        nood = 0
+        nood = nexact = 0
         for c0 in range(0, N_PER_GRAPH, CHUNK):
-            y, nbad = res[(gi, c0)]
+            y, nbad, nex = res[(gi, c0)]
             nood += nbad
+            nexact += nex
             s += y.sum(0); s2 += (y * y).sum(0)
             for c in ucls:
                 yc = sum(y[:, e] for e in range(y.shape[1]) if cls[e] == c)
                 cs[c] += float(yc.sum()); cs2[c] += float((yc * yc).sum())
             yt = y.sum(1)
             ts += float(yt.sum()); ts2 += float((yt * yt).sum())
-        out['graphs'].append(dict(graph=gi, n=N_PER_GRAPH, n_ood=nood, sum=s.tolist(), sum2=s2.tolist(),
+        out['graphs'].append(dict(graph=gi, n=N_PER_GRAPH, n_ood=nood, n_exact=nexact, sum=s.tolist(), sum2=s2.tolist(),
                                   classes=[list(c) for c in ucls], csum=[cs[c] for c in ucls],
                                   csum2=[cs2[c] for c in ucls], tsum=ts, tsum2=ts2))
     with open(os.path.join(HERE, 'oracle_estimates_3loop.json'), 'w') as f:

@@ -398,3 +398,4 @@ def test_generated_code_matches_interpreter(amm):
             assert np.all(d <= (Bg + Bi).cpu().numpy() + 1e-300)
     finally:
         amm.set_generated(True)
+
