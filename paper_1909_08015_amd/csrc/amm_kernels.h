@@ -184,6 +184,10 @@ __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, c
             double ye = ldexp(I[e].v / o.gx, -o.gj);
             r += ldexp(I[e].a / o.gx, -o.gj);
             if (!isfinite(ye)) flag = 1;
+            // the running bound is first order: where it is not small against
+            // the value's scale, second-order terms may exceed it, so the
+            // point is recomputed whatever the threshold
+            if (!(KAPPA * 0x1p-53 * I[e].a <= 1e-2 * fmax(fabs(I[e].v), aI[e].v))) flag = 1;
             y[e] = ye;
         }
         if (!(KAPPA * 0x1p-53 * r <= A.tau)) flag = 1;

@@ -181,6 +181,16 @@ def test_four_loop_fp64_within_bound_of_double_double(four_loops):
         # only accurate for most points
         assert np.median(np.abs(A64 - Add) / Add) < 1e-10
         cert.append(B64 <= 1e-10 * np.maximum(np.abs(Idd), Add))
+        # the Monte Carlo pass flags every point outside the first-order regime
+        # whatever the threshold (here one no bound reaches): its flag count
+        # equals the number of points with a bound above 1e-2 of the FP64
+        # value's scale in some insertion (the same FP64 numbers)
+        outside = ~np.all(B64 <= 1e-2 * np.maximum(np.abs(I64), A64), axis=1)
+        nonfinite = ~np.all(np.isfinite(I64), axis=1)
+        if bool(keep.all()):
+            amm.integrate(seed=0, n_per_graph=256, graph_begin=gi, graph_end=gi + 1, accept_tau=[1e300])
+            r = amm.read(gi, -1)
+            assert r['n_flag'] == int((outside | nonfinite).sum()), (gi, r['n_flag'], int(outside.sum()))
     assert np.concatenate([c.ravel() for c in cert]).mean() > 0.05
 
 
