@@ -120,3 +120,60 @@ def test_density_exponents_keep_the_variance_finite(n):
         violations_uncapped += int((mix_old >= 2 * slope - 0.01).sum())
     if n == 3:
         assert violations_uncapped > 0
+
+
+def test_four_loop_faces_graph0():
+    """4-loop SE graph 0 (its polynomials from the oracle's committed cache):
+    every one of the 2046 proper subsets of lines scaled by rho = 1e-6 and
+    1e-7 at a seeded base point: slope >= 0.99 for the subtracted integrand
+    of every insertion, and the capped density exponent Deg1(s) stays at or
+    below it (f/g bounded); the unsubtracted A_G f_G is divergent (slope <=
+    0.01) on the line set of every proper UV subgraph (negative control).
+
+    The rho pair is shallower than at 2 and 3 loops because the cancellation
+    between the forest terms, sum|terms| / |I|, grows like rho^-2 on nested
+    faces and reaches 1.1e16 at rho = 1e-7: the x87 sum (64-bit significand)
+    then still carries |I| to about 1e-3, and the pair is checked to stay
+    inside that range.  Deeper (rho ~ 1e-10) the cancellation passes 1e20 and
+    the x87 value is noise."""
+    I.load_poly_cache(os.path.join(GOLD, 'oracle_level_polys_4loop_g0.json.gz'))
+    n, gi, M = 4, 0, 11
+    ch = G.se_graphs(n)[gi]
+    rng = np.random.default_rng(400)
+    base = rng.random(M) + 0.2
+    base /= base.sum()
+    vgs = [G.make_vertex_graph(ch, e) for e in range(2 * n - 1)]
+    uv = sorted({s for vg in vgs for s in _uv_line_sets(vg)})
+    subsets = list(range(1, (1 << M) - 1))
+    rho = (np.longdouble('1e-6'), np.longdouble('1e-7'))
+    Z = []
+    for s in subsets:
+        for r in rho:
+            z = np.array([np.longdouble(base[i]) * (r if (s >> i) & 1 else 1) for i in range(M)], dtype=np.longdouble)
+            Z.append(z / z.sum())
+    Z = np.array(Z)
+    cols = [Z[:, i] for i in range(M)]
+    k = np.array([bin(s).count('1') for s in subsets], dtype=np.longdouble)
+
+    def slopes(vals):
+        v = np.abs(np.asarray(vals, dtype=np.longdouble)).reshape(len(subsets), 2)
+        return ((np.log(v[:, 1] * rho[1] ** k) - np.log(v[:, 0] * rho[0] ** k)) / np.log(rho[1] / rho[0])).astype(float)
+    n_uv = 0
+    smin = np.full(len(subsets), np.inf)
+    with np.errstate(all='ignore'):
+        for vg in vgs:
+            v, a = I.vertex_integrand(vg, cols, exact='ld')
+            canc = np.asarray(a, dtype=np.longdouble) / np.abs(np.asarray(v, dtype=np.longdouble))
+            assert float(canc.max()) * 2.0 ** -63 < 2e-3, float(canc.max())
+            sl = slopes(v)
+            smin = np.minimum(smin, sl)
+            assert sl.min() >= 0.99, (sl.min(), subsets[int(np.argmin(sl))])
+            t0 = [t for t in G.terms(vg) if len(t.forest) == 1][0]
+            r, _ = I.term_value(vg, t0, cols, 'ld')
+            su = slopes(r)
+            for s in _uv_line_sets(vg):
+                assert su[subsets.index(s)] <= 0.01, (s, su[subsets.index(s)])
+                n_uv += 1
+    assert n_uv >= 7 and len(uv) >= 3
+    deg1 = S.Density(n, ch).deg1[subsets]
+    assert np.all(deg1 <= smin + 0.01), float((deg1 - smin).max())
