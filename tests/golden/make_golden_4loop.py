@@ -32,7 +32,7 @@ from oracle.philox import uniforms, graph_uid   # noqa: E402
 N_LOOPS = 4
 GRAPHS = [0, 7, 14, 21, 28, 35, 42, 49, 56, 63, 70, 73]
 COUNTERS = list(range(0, 256))
-N_EXACT = 2
+N_EXACT = 4
 POLY_CACHE = os.environ.get('AMM_GOLDEN4_POLYS', '')
 
 

@@ -5,7 +5,7 @@ tests/golden/oracle_points_4loop.npz (written by make_golden_4loop.py, oracle
 only) holds, for 12 of the 74 four-loop SE graphs, seed-0 counters 0..255: the
 oracle's points, densities and paths, every insertion integrand and its sum
 of |term| in x87 extended precision (hi + lo doubles), and exact rational
-values at the first two counters.  Checked here through the C ABI:
+values at the first four counters.  Checked here through the C ABI:
   * sampling bit-exact (points, g = gx 2^gj, components, sector paths);
   * FP64 integrands within their own round-off bound B wherever they are
     finite, and within 1e-10 of max(|I|, sum|terms|) wherever B certifies
