@@ -513,12 +513,19 @@ struct PlanDev {
     int nterms;
     int n;
     int ninsert;
+    // FP64 interpreter tables: the group stream (four monomials per record,
+    // see poly_groups) and, per range, its first word and number of records
+    const uint32_t *gwords;
+    const int2 *granges;
+    int ngwords;
 };
 
 template <int N> struct Dims {
     static constexpr int KM = 2 * N;
     static constexpr int NV = KM * (KM + 1) / 2 + 2 * KM;
+    static constexpr int NVL = NV + 1;      // LDS columns: the variables and the constant-1 slot
     static constexpr int DEPTH = 2 * N + 1;
+    static_assert(NV == amm_nvars(N), "variable slots");
 };
 
 // Sum of the monomials coef * prod vars of one range.  Generic arithmetic,
@@ -564,89 +571,126 @@ AMM_HDI int wave_uniform(int x) {
 #endif
 }
 
-// Sum of a range in FP64 (Tv = double) or FP64 with the first-order bound
-// (Tv = ea), four monomials at a time on independent accumulators: their
-// variable reads and products are in flight together.  Past its degree a
-// monomial reads variable 0 and multiplies by exactly 1 (branch-free).  The
-// four partial sums are added at the end; for the bound each addition adds
-// |its result|.
-// A monomial at a wave-uniform address, read with scalar loads (the table
-// words land in scalar registers, so decoding the variable indices costs no
-// vector instructions).
-AMM_HDI MonoRegs load_mono_uniform(const Mono *p) {
+// The FP64 interpreter's monomial table: the group stream.  Each range (the
+// monomials of one (level, variant, output, c), sorted by degree) is cut into
+// records of four consecutive monomials:
+//   word 0      K, the largest degree of the four;  word 1: 0
+//   words 2-9   the four coefficients (double, low word first; 0 past the
+//               range's end)
+//   words 10..  4K variable indices, factor-major: index i of monomial q at
+//               10 + 4i + q; a monomial of degree below K, and a padding
+//               monomial, use the constant-1 slot amm_nvars(n)
+// so a record is 10 + 4K words.  Multiplying by the exact 1 leaves a product
+// unchanged, so every monomial is still coef * x_1 ... x_nv in index order.
+// The indices go to scalar registers with scalar loads: one vector address
+// operation, one LDS read and one multiply per factor.
 #if defined(__HIP_DEVICE_COMPILE__)
+typedef const uint32_t __attribute__((address_space(4))) *GroupWords;
+AMM_HDI GroupWords uniform_words(const uint32_t *p) {
     const uint64_t a = (uint64_t)(const void *)p;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a), hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
-    typedef const uint64_t __attribute__((address_space(4))) *cptr;
-    const cptr q = (cptr)(((uint64_t)hi << 32) | lo);
-    MonoRegs r;
-    r.coef = __builtin_bit_cast(double, q[0]);
-    r.w1 = q[1];
-    r.w2 = q[2];
-    return r;
+    return (GroupWords)(((uint64_t)hi << 32) | lo);
+}
 #else
-    return load_mono(p);
+typedef const uint32_t *GroupWords;
+AMM_HDI GroupWords uniform_words(const uint32_t *p) { return p; }
+#endif
+constexpr int GROUP_HEAD = 10;
+
+// Software prefetch of the group stream into L2.  Without it the scalar loads
+// of the records wait on HBM every few records: the streams of a 4-loop graph
+// set do not fit in L2, and each wave walks its graph's stream once per 64
+// samples.  Every few records, lanes 0-15 load one word from each of the 16
+// 64-byte lines that start 1 KB past the current record (clamped to the
+// stream), through the vector memory path, whose counter the LDS waits do not
+// share.  A loaded word is consumed (XORed into a carried word) at the next
+// prefetch, before the new load is issued, so the load can land in the same
+// register and its latency is never waited for in the loop; drain() consumes
+// the last one at the end of a sample.
+struct TablePf {
+    uint32_t acc = 0, pend = 0;
+};
+AMM_HDI void table_prefetch(const PlanDev &P, int word, TablePf &pf) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint32_t last = (uint32_t)P.ngwords - 1u;
+    uint32_t w = (uint32_t)word + 256u + (threadIdx.x & 15u) * 16u;
+    w = w < last ? w : last;
+    typedef const uint32_t __attribute__((address_space(1))) *gptr;
+    pf.acc ^= pf.pend;
+    asm volatile("" : "+v"(pf.acc) : : "memory");
+    pf.pend = *((gptr)(const void *)P.gwords + w);
+#endif
+}
+AMM_HDI void table_drain(TablePf &pf) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint32_t w = pf.acc ^ pf.pend;
+    asm volatile("" ::"v"(w));
+    pf.acc = pf.pend = 0;
 #endif
 }
 
-// Sum of a range in FP64 (Bound = false) or FP64 with the first-order bound,
-// four monomials at a time on independent accumulators so that their variable
-// reads and products are in flight together; the range, the table words and
-// the degrees are wave-uniform, so the degree tests are scalar branches.  The
-// bound term of a monomial, |p| (nv (rmax + 1) + 1), is kept as the two sums
-// of |p| nv and |p|; each accumulation adds |partial sum|, and so does each
+// p[q] *= x_{I0} ... x_{I0+K-1} of monomial q of the record at w: the 4K LDS
+// reads are issued together, then the products in index order.
+template <int K, int I0, typename Vars>
+AMM_HDI void group_factors(GroupWords w, const Vars &vars, double (&p)[4]) {
+    double x[K][4];
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[i][q] = vars.val((int)w[GROUP_HEAD + 4 * (I0 + i) + q]);
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) p[q] = p[q] * x[i][q];
+}
+
+// Sum of a range over its records in FP64 (Bound = false) or FP64 with the
+// first-order bound, the four monomials of a record on four accumulators.
+// The bound term of a monomial, |p| (nv (rmax + 1) + 1), is taken with the
+// record's K for nv (at least the monomial's degree) and kept as the two sums
+// of |p| K and |p|; each accumulation adds |partial sum|, and so does each
 // addition of the four partial sums at the end.
 template <bool Bound, typename Vars>
-AMM_HDI void poly_sum4(const PlanDev &P, int2 r, const Vars &vars, double r1, double &sum, double &err) {
-    const int beg = wave_uniform(r.x), end = wave_uniform(r.y);
+AMM_HDI void poly_groups(const PlanDev &P, int2 gr, Vars &vars, double r1, double &sum, double &err) {
+    const int w0 = wave_uniform(gr.x), ng = wave_uniform(gr.y);
+    const GroupWords W = uniform_words(P.gwords);
     double av[4] = {0.0, 0.0, 0.0, 0.0}, an[4] = {0.0, 0.0, 0.0, 0.0}, aa[4] = {0.0, 0.0, 0.0, 0.0};
-    int m = beg;
-    for (; m + 4 <= end; m += 4) {
-        MonoRegs mo[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) mo[q] = load_mono_uniform(P.monos + m + q);
-        int k[4], kmin = MAXMONO_VARS + 1, kmax = 0;
+    int off = w0;
+    for (int g = 0; g < ng; ++g) {
+        if ((g & 7) == 0) table_prefetch(P, off, vars.pf);
+        const GroupWords w = W + off;
+        const int K = (int)w[0];
         double p[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            k[q] = mo[q].nv();
-            kmax = k[q] > kmax ? k[q] : kmax;
-            kmin = k[q] < kmin ? k[q] : kmin;
-            p[q] = mo[q].coef;
-        }
-        // ranges are sorted by degree, so the four degrees nearly always agree
-        int i = 0;
-        for (; i < kmin; ++i) {
-            double x[4];
+        for (int q = 0; q < 4; ++q) p[q] = __builtin_bit_cast(double, (uint64_t)w[2 + 2 * q] | ((uint64_t)w[3 + 2 * q] << 32));
+        switch (K) {
+        case 0: break;
+        case 1: group_factors<1, 0>(w, vars, p); break;
+        case 2: group_factors<2, 0>(w, vars, p); break;
+        case 3: group_factors<3, 0>(w, vars, p); break;
+        case 4: group_factors<4, 0>(w, vars, p); break;
+        case 5: group_factors<5, 0>(w, vars, p); break;
+        case 6: group_factors<3, 0>(w, vars, p); group_factors<3, 3>(w, vars, p); break;
+        case 7: group_factors<4, 0>(w, vars, p); group_factors<3, 4>(w, vars, p); break;
+        case 8: group_factors<4, 0>(w, vars, p); group_factors<4, 4>(w, vars, p); break;
+        default:
+            group_factors<4, 0>(w, vars, p);
+            group_factors<4, 4>(w, vars, p);
+            for (int i = 8; i < K; ++i) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) x[q] = vars.val(mo[q].var(i));
-#pragma unroll
-            for (int q = 0; q < 4; ++q) p[q] = p[q] * x[q];
+                for (int q = 0; q < 4; ++q) p[q] = p[q] * vars.val((int)w[GROUP_HEAD + 4 * i + q]);
+            }
         }
-        for (; i < kmax; ++i) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (i < k[q]) p[q] = p[q] * vars.val(mo[q].var(i));
-        }
+        const double kd = (double)K;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             av[q] = av[q] + p[q];
             if (Bound) {
-                an[q] = fma(fabs(p[q]), (double)k[q], an[q]);
+                an[q] = fma(fabs(p[q]), kd, an[q]);
                 aa[q] = (aa[q] + fabs(p[q])) + fabs(av[q]);
             }
         }
-    }
-    for (; m < end; ++m) {
-        const MonoRegs mo = load_mono_uniform(P.monos + m);
-        const int nv = mo.nv();
-        double p = mo.coef;
-        for (int i = 0; i < nv; ++i) p = p * vars.val(mo.var(i));
-        av[0] = av[0] + p;
-        if (Bound) {
-            an[0] = fma(fabs(p), (double)nv, an[0]);
-            aa[0] = (aa[0] + fabs(p)) + fabs(av[0]);
-        }
+        off += GROUP_HEAD + 4 * K;
     }
     const double s01 = av[0] + av[1], s23 = av[2] + av[3];
     sum = s01 + s23;
@@ -655,19 +699,32 @@ AMM_HDI void poly_sum4(const PlanDev &P, int2 r, const Vars &vars, double r1, do
               ((fabs(s01) + fabs(s23)) + fabs(sum));
 }
 
+// Range table entry at a wave-uniform index (scalar load).
+AMM_HDI int2 load_range_uniform(const int2 *t, int i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint64_t a = (uint64_t)(const void *)(t + wave_uniform(i));
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a), hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    typedef const int2 __attribute__((address_space(4))) *cptr;
+    return *(cptr)(((uint64_t)hi << 32) | lo);
+#else
+    return t[i];
+#endif
+}
+
 template <typename T, typename Vars>
-AMM_HDI T poly_range(const PlanDev &P, int2 r, const Vars &vars, double rmax) {
+AMM_HDI T poly_range(const PlanDev &P, int ri, Vars &vars, double rmax) {
     if constexpr (std::is_same<T, ea>::value) {
         double av = 0.0, ae = 0.0;
-        poly_sum4<true>(P, r, vars, rmax + 1.0, av, ae);
+        poly_groups<true>(P, load_range_uniform(P.granges, ri), vars, rmax + 1.0, av, ae);
         return ea(av, ae);
     } else if constexpr (std::is_same<T, double>::value) {
         double av = 0.0, ae = 0.0;
-        poly_sum4<false>(P, r, vars, 0.0, av, ae);
+        poly_groups<false>(P, load_range_uniform(P.granges, ri), vars, 0.0, av, ae);
         return av;
     } else if constexpr (std::is_same<T, dd>::value) {
         // two monomials per step on separate accumulators (independent
         // dependency chains), the next two already loading
+        const int2 r = P.ranges[ri];
         dd acc0(0.0), acc1(0.0);
         const int m0 = r.x < r.y ? r.x : 0;
         MonoRegs na = load_mono(P.monos + m0);
@@ -698,6 +755,7 @@ AMM_HDI T poly_range(const PlanDev &P, int2 r, const Vars &vars, double rmax) {
         }
         return acc0 + acc1;
     } else {
+        const int2 r = P.ranges[ri];
         T acc = T(0.0);
         for (int m = r.x; m < r.y; ++m) {
             const MonoRegs mo = load_mono(P.monos + m);
@@ -731,10 +789,15 @@ AMM_HDI void conv_into(const T *a, const T *b, T *out) {
 // private array (double-double path); VarsLds keeps one LDS column per thread
 // (address base + i * stride, conflict-free for wave-uniform i).  For the
 // magnitude type only the values are stored; the magnitude of a variable is
-// |v| times the level's largest magnitude/value ratio.
+// |v| times the level's largest magnitude/value ratio.  Slot amm_nvars(n)
+// holds the constant 1 that pads the FP64 group stream: VarsPriv sets it, the
+// kernels set it in their LDS columns (set_one_slot) before evaluating.
 template <typename T, int NV> struct VarsPriv {
-    T v[NV];
+    T v[NV + 1];            // the variables and the constant-1 slot
+    TablePf pf;
+    AMM_HDI VarsPriv() { v[NV] = T(1.0); }
     AMM_HDI void begin() {}
+    AMM_HDI void drain() { table_drain(pf); }
     AMM_HDI void set(int i, const T &x) { v[i] = x; }
     AMM_HDI T get(int i) const { return v[i]; }
     AMM_HDI double val(int i) const { return to_double(v[i]); }
@@ -747,16 +810,22 @@ template <typename T, int NV> struct VarsPriv {
 struct VarsLdsD {
     double *base;
     int stride;
+    TablePf pf;
     AMM_HDI void begin() {}
+    AMM_HDI void drain() { table_drain(pf); }
     AMM_HDI void set(int i, double x) { base[i * stride] = x; }
     AMM_HDI double get(int i) const { return base[i * stride]; }
     AMM_HDI double val(int i) const { return base[i * stride]; }
 };
+template <int N>
+AMM_HDI void set_one_slot(double *column, int stride) { column[Dims<N>::NV * stride] = 1.0; }
 struct VarsLdsEa {
     double *base;      // values, one LDS column per thread
     int stride;
     double rmax;       // largest relative error bound of the variables set since begin()
+    TablePf pf;
     AMM_HDI void begin() { rmax = 0.0; }
+    AMM_HDI void drain() { table_drain(pf); }
     AMM_HDI void set(int i, const ea &x) {
         base[i * stride] = x.v;
         rmax = fmax(rmax, relerr(x));
@@ -947,8 +1016,7 @@ AMM_HDI void eval_level(const PlanDev &P, const LevelDesc &d, const double *z, T
             T fac = base;
 #pragma unroll
             for (int c = 0; c < N; ++c) {
-                int2 r = P.ranges[d.mono_range + (var * d.nout + o) * (P.n + 1) + c];
-                T acc = poly_range<T>(P, r, vars, rmax);
+                T acc = poly_range<T>(P, d.mono_range + (var * d.nout + o) * (P.n + 1) + c, vars, rmax);
                 own[c] = acc * fac;
                 fac = fac * T(-0.5);
             }
@@ -1000,6 +1068,7 @@ AMM_HDI void eval_graph(const PlanDev &P, const double *z, T *I, T *absI, Vars &
         I[td.e] += sv;
         absI[td.e] += absd(val);
     }
+    vars.drain();
 }
 
 // Private-storage convenience overload (host tests, double-double path).

@@ -86,6 +86,9 @@ struct GraphSlot {
     int32_t *d_ops = nullptr;
     Mono *d_monos = nullptr;
     int2 *d_ranges = nullptr;
+    uint32_t *d_gwords = nullptr;             // FP64 group stream and its ranges
+    int2 *d_granges = nullptr;
+    int ngwords = 0;
     double *d_deg1 = nullptr, *d_deg3 = nullptr, *d_W1 = nullptr, *d_logdeg1 = nullptr;
     float *d_ptheta = nullptr;                // learned P_theta(j|s) [2^M * M]
     double *d_pilotW = nullptr;               // pilot W(s, j) [2^M * M]
@@ -96,6 +99,7 @@ struct GraphSlot {
         PlanDev p;
         p.levels = d_levels; p.terms = d_terms; p.ops = d_ops; p.monos = d_monos; p.ranges = d_ranges;
         p.nterms = (int)plan.terms.size(); p.n = n; p.ninsert = ne;
+        p.gwords = d_gwords; p.granges = d_granges; p.ngwords = ngwords;
         return p;
     }
     DensityDev dens_dev(bool learned) const {

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <algorithm>
@@ -51,6 +52,7 @@ amm_ctx::~amm_ctx() {
     if (fork_ev) hipEventDestroy(fork_ev);
     for (auto &s : slots) {
         hipFree(s.d_levels); hipFree(s.d_terms); hipFree(s.d_ops); hipFree(s.d_monos); hipFree(s.d_ranges);
+            hipFree(s.d_gwords); hipFree(s.d_granges);
         hipFree(s.d_deg1); hipFree(s.d_deg3); hipFree(s.d_W1); hipFree(s.d_logdeg1);
         hipFree(s.d_ptheta); hipFree(s.d_pilotW);
     }
@@ -199,6 +201,44 @@ int upload(X **dst, const X *src, size_t count) {
     HIPCHK(hipMalloc((void **)dst, count * sizeof(X)));
     if (src) HIPCHK(hipMemcpy(*dst, src, count * sizeof(X), hipMemcpyHostToDevice));
     return AMM_OK;
+}
+
+// The FP64 interpreter's group stream of a plan (layout in amm_core.h): every
+// range of the monomial table cut into records of four consecutive monomials,
+// padded with the constant-1 slot (short monomials) and zero coefficients
+// (the range's last record).  Identical ranges share their records.
+static void group_stream(const PlanHost &P, std::vector<uint32_t> &words, std::vector<int2> &granges) {
+    const uint32_t one = (uint32_t)amm_nvars(P.n);
+    std::map<std::pair<int, int>, int2> done;
+    words.clear();
+    granges.resize(P.ranges.size());
+    for (size_t ri = 0; ri < P.ranges.size(); ++ri) {
+        const auto r = P.ranges[ri];
+        auto it = done.find(r);
+        if (it != done.end()) { granges[ri] = it->second; continue; }
+        const int2 g = make_int2((int)words.size(), (r.second - r.first + 3) / 4);
+        for (int m = r.first; m < r.second; m += 4) {
+            int K = 0;
+            for (int q = 0; q < 4 && m + q < r.second; ++q) K = std::max(K, (int)P.monos[m + q].nv);
+            words.push_back((uint32_t)K);
+            words.push_back(0u);
+            for (int q = 0; q < 4; ++q) {
+                const double c = m + q < r.second ? P.monos[m + q].coef : 0.0;
+                uint64_t b;
+                std::memcpy(&b, &c, 8);
+                words.push_back((uint32_t)b);
+                words.push_back((uint32_t)(b >> 32));
+            }
+            for (int i = 0; i < K; ++i)
+                for (int q = 0; q < 4; ++q) {
+                    const bool has = m + q < r.second && i < (int)P.monos[m + q].nv;
+                    words.push_back(has ? (uint32_t)P.monos[m + q].v[i] : one);
+                }
+        }
+        granges[ri] = g;
+        done.emplace(r, g);
+    }
+    if (words.empty()) words.push_back(0u);
 }
 
 int grid_for(uint64_t n) { return (int)((n + BLOCK - 1) / BLOCK); }
@@ -364,6 +404,7 @@ int amm_enumerate(amm_ctx *c, int loops, int *n_se, int *n_vertex, int *M) {
         hipSetDevice(c->device);
         for (auto &s : c->slots) {
             hipFree(s.d_levels); hipFree(s.d_terms); hipFree(s.d_ops); hipFree(s.d_monos); hipFree(s.d_ranges);
+            hipFree(s.d_gwords); hipFree(s.d_granges);
             hipFree(s.d_deg1); hipFree(s.d_deg3); hipFree(s.d_W1); hipFree(s.d_logdeg1);
             hipFree(s.d_ptheta); hipFree(s.d_pilotW);
         }
@@ -452,12 +493,20 @@ int amm_build_tables(amm_ctx *c, const amm_density_params *params, int gb, int g
         s.ncls = (int)ucls.size();
         for (int q = 0; q < s.ncls; ++q) for (int w = 0; w < 3; ++w) s.cls_kmm[q][w] = ucls[q][w];
         hipFree(s.d_levels); hipFree(s.d_terms); hipFree(s.d_ops); hipFree(s.d_monos); hipFree(s.d_ranges);
+            hipFree(s.d_gwords); hipFree(s.d_granges);
         hipFree(s.d_deg1); hipFree(s.d_deg3); hipFree(s.d_W1); hipFree(s.d_logdeg1);
         std::vector<int2> rg(s.plan.ranges.size());
         for (size_t i = 0; i < rg.size(); ++i) rg[i] = make_int2(s.plan.ranges[i].first, s.plan.ranges[i].second);
         int rc;
         s.d_levels = nullptr; s.d_terms = nullptr; s.d_ops = nullptr; s.d_monos = nullptr; s.d_ranges = nullptr;
+        s.d_gwords = nullptr; s.d_granges = nullptr; s.ngwords = 0;
         if (plans) {
+            std::vector<uint32_t> gw;
+            std::vector<int2> gr;
+            group_stream(s.plan, gw, gr);
+            s.ngwords = (int)gw.size();
+            if ((rc = upload(&s.d_gwords, gw.data(), gw.size()))) return rc;
+            if ((rc = upload(&s.d_granges, gr.data(), gr.size()))) return rc;
             if ((rc = upload(&s.d_levels, s.plan.levels.data(), s.plan.levels.size()))) return rc;
             if ((rc = upload(&s.d_terms, s.plan.terms.data(), s.plan.terms.size()))) return rc;
             if ((rc = upload(&s.d_ops, s.plan.ops.data(), s.plan.ops.size()))) return rc;

@@ -85,7 +85,8 @@ __global__ void __launch_bounds__(BLOCK) k_eval(Ev EV, const double *z, uint64_t
     for (int j = 0; j < M; ++j) zz[j] = z[i * M + j];
     T v[NE], a[NE];
     if constexpr (std::is_same<T, ea>::value && Ev::kLds) {
-        __shared__ double vlds[Dims<N>::NV * BLOCK];
+        __shared__ double vlds[Dims<N>::NVL * BLOCK];
+        set_one_slot<N>(vlds + threadIdx.x, BLOCK);
         VarsLdsEa vars{vlds + threadIdx.x, BLOCK, 0.0};
         EV.template eval<T, N>(zz, v, a, vars);
     } else {
@@ -156,7 +157,10 @@ __device__ __forceinline__ void eval_sample(const Ev &EV, const DensityDev &D, c
         return;
     }
     bool plain = false;
-    if constexpr (Ev::kLds) plain = A.tau == INFINITY;    // interpreter: skip bounds if unchecked
+    if constexpr (Ev::kLds) {
+        plain = A.tau == INFINITY;                       // interpreter: skip bounds if unchecked
+        set_one_slot<N>(vlds + threadIdx.x, NB);
+    }
     if (plain) {
         if constexpr (Ev::kLds) {
             double I[NE], aI[NE];
@@ -282,7 +286,7 @@ __global__ void __launch_bounds__(Ev::kBlock) k_integrate(Ev EV, DensityDev D, R
     constexpr int NB = Ev::kBlock;
     __shared__ double shs[NB / 64][NST];
     __shared__ int shw[NB / 64];
-    __shared__ double vlds[(Ev::kLds ? Dims<N>::NV : 1) * NB];
+    __shared__ double vlds[(Ev::kLds ? Dims<N>::NVL : 1) * NB];
     for (int ch = blockIdx.x; ch < A.nchunks; ch += gridDim.x)
         process_chunk<N>(EV, D, A, ch, part + (size_t)ch * NSTAT_MAX, flags + (size_t)ch * CHUNK, nflag + ch, shs,
                          shw, vlds);
@@ -301,7 +305,7 @@ __global__ void __launch_bounds__(InterpEval::kBlock) __attribute__((amdgpu_wave
     constexpr int NB = InterpEval::kBlock;
     __shared__ double shs[NB / 64][NST];
     __shared__ int shw[NB / 64];
-    __shared__ double vlds[Dims<N>::NV * NB];
+    __shared__ double vlds[Dims<N>::NVL * NB];
     __shared__ int item;
     for (;;) {
         if (threadIdx.x == 0) item = atomicAdd(work, 1);
@@ -363,6 +367,7 @@ struct VarsLdsDd {
     double *hi, *lo;
     int stride;
     AMM_HDI void begin() {}
+    AMM_HDI void drain() {}
     AMM_HDI void set(int i, const dd &x) { hi[i * stride] = x.hi; lo[i * stride] = x.lo; }
     AMM_HDI dd get(int i) const { return dd(hi[i * stride], lo[i * stride]); }
 };

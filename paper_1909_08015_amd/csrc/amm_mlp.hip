@@ -32,7 +32,8 @@ template <int N>
 __global__ void __launch_bounds__(BLOCK) k_pilot_w(PlanDev P, DensityDev D, uint32_t uid, uint64_t seed, uint64_t c0,
                                                    uint64_t n, double *wbuf) {
     constexpr int M = 3 * N - 1, NE = 2 * N - 1;
-    __shared__ double vlds[Dims<N>::NV * BLOCK];
+    __shared__ double vlds[Dims<N>::NVL * BLOCK];
+    set_one_slot<N>(vlds + threadIdx.x, BLOCK);
     uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     double u[2 * M], z[M];

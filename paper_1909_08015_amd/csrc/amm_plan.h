@@ -28,6 +28,10 @@ struct Mono {
 //   x_{kk'} (1 <= k <= k' <= K) at xidx(K, k, k'), then A_k at XN(K) + k - 1,
 //   then C_k at XN(K) + K + k - 1.
 __host__ __device__ inline int amm_xn(int K) { return K * (K + 1) / 2; }
+// Number of variable slots of a level at n loops (K <= 2n segments); the slot
+// with this index holds the constant 1 in the FP64 interpreter (padding of
+// monomial groups, see the group stream in amm_core.h).
+__host__ __device__ constexpr int amm_nvars(int n) { return (2 * n) * (2 * n + 1) / 2 + 2 * (2 * n); }
 __host__ __device__ inline int amm_xidx(int K, int k, int k2) {
     return (k - 1) * (2 * K - k + 2) / 2 + (k2 - k);
 }
