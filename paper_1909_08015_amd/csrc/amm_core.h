@@ -647,19 +647,28 @@ AMM_HDI void group_factors(GroupWords w, const Vars &vars, double (&p)[4]) {
 // Sum of a range over its records in FP64 (Bound = false) or FP64 with the
 // first-order bound, the four monomials of a record on four accumulators.
 // The bound term of a monomial, |p| (nv (rmax + 1) + 1), is taken with the
-// record's K for nv (at least the monomial's degree) and kept as the two sums
-// of |p| K and |p|; each accumulation adds |partial sum|, and so does each
-// addition of the four partial sums at the end.
+// record's K for nv (at least the monomial's degree), one fma per monomial;
+// each accumulation adds |partial sum|, and so does each addition of the four
+// partial sums at the end.
 template <bool Bound, typename Vars>
 AMM_HDI void poly_groups(const PlanDev &P, int2 gr, Vars &vars, double r1, double &sum, double &err) {
     const int w0 = wave_uniform(gr.x), ng = wave_uniform(gr.y);
     const GroupWords W = uniform_words(P.gwords);
     double av[4] = {0.0, 0.0, 0.0, 0.0}, an[4] = {0.0, 0.0, 0.0, 0.0}, aa[4] = {0.0, 0.0, 0.0, 0.0};
     int off = w0;
+    uint32_t touch = 0;
+    const int lastw = P.ngwords - 1;
     for (int g = 0; g < ng; ++g) {
         if ((g & 7) == 0) table_prefetch(P, off, vars.pf);
         const GroupWords w = W + off;
         const int K = (int)w[0];
+        {
+            // bring the next record's two lines into the scalar cache while
+            // this record's variable reads are in flight
+            const int nx = off + GROUP_HEAD + 4 * K;
+            const int n2 = nx + 16;
+            touch ^= W[nx < lastw ? nx : lastw] ^ W[n2 < lastw ? n2 : lastw];
+        }
         double p[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) p[q] = __builtin_bit_cast(double, (uint64_t)w[2 + 2 * q] | ((uint64_t)w[3 + 2 * q] << 32));
@@ -681,21 +690,24 @@ AMM_HDI void poly_groups(const PlanDev &P, int2 gr, Vars &vars, double r1, doubl
                 for (int q = 0; q < 4; ++q) p[q] = p[q] * vars.val((int)w[GROUP_HEAD + 4 * i + q]);
             }
         }
-        const double kd = (double)K;
+        const double cK = fma((double)K, r1, 1.0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             av[q] = av[q] + p[q];
             if (Bound) {
-                an[q] = fma(fabs(p[q]), kd, an[q]);
-                aa[q] = (aa[q] + fabs(p[q])) + fabs(av[q]);
+                an[q] = fma(fabs(p[q]), cK, an[q]);
+                aa[q] = aa[q] + fabs(av[q]);
             }
         }
         off += GROUP_HEAD + 4 * K;
     }
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" ::"s"(touch));
+#endif
     const double s01 = av[0] + av[1], s23 = av[2] + av[3];
     sum = s01 + s23;
     if (Bound)
-        err = fma((an[0] + an[1]) + (an[2] + an[3]), r1, (aa[0] + aa[1]) + (aa[2] + aa[3])) +
+        err = ((an[0] + an[1]) + (an[2] + an[3])) + ((aa[0] + aa[1]) + (aa[2] + aa[3])) +
               ((fabs(s01) + fabs(s23)) + fabs(sum));
 }
 
