@@ -56,9 +56,16 @@ def cpu_baseline(seconds_target=15.0):
         pool.map(_oracle_chunk, [(4, 0, 10 ** 6 + 1000 * k, 8, cache) for k in range(cores)])   # load caches
         dt1 = max(pool.map(_oracle_chunk, [(4, 0, 1000 * k, probe, cache) for k in range(cores)]))
         n = max(probe, int(probe * seconds_target / max(dt1, 1e-3)))
-        t0 = time.perf_counter()
-        pool.map(_oracle_chunk, [(4, 0, 2 * 10 ** 6 + n * k, n, cache) for k in range(cores)])
-        dt = time.perf_counter() - t0
+        for _ in range(3):
+            # the probe's time per point is inflated by per-call costs that
+            # larger chunks amortise: resize from the timed run while it comes
+            # out far too short
+            t0 = time.perf_counter()
+            pool.map(_oracle_chunk, [(4, 0, 2 * 10 ** 6 + n * k, n, cache) for k in range(cores)])
+            dt = time.perf_counter() - t0
+            if dt >= 0.5 * seconds_target:
+                break
+            n = int(n * seconds_target / max(dt, 1e-3))
     cpu = platform.processor() or platform.machine()
     try:
         for line in open('/proc/cpuinfo'):
