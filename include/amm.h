@@ -122,9 +122,9 @@ int amm_graph_desc(const amm_ctx *ctx, int g, int *chords, int *classes);
 /* Build the per-graph density tables (Sec. III.A) and subtraction tables
  * (Sec. II forest formula) for graphs [graph_begin, graph_end) of the
  * enumerated loop order and upload them once.  params NULL = Calc 2.
- * At 5 loops the integrand tables hold about 3 million monomials (70 MB) per
- * graph and take minutes per graph to build on one host core (graphs are
- * built on a thread pool); AMM_OPT_PLANS = 0 builds the density tables alone. */
+ * At 5 loops the integrand tables hold about 3 million monomials per graph
+ * (70 MB each for the double-double table and the FP64 group stream) and take
+ * minutes per graph to build (a thread pool); AMM_OPT_PLANS = 0: density only. */
 int amm_build_tables(amm_ctx *ctx, const amm_density_params *params,
                      int graph_begin, int graph_end);
 
